@@ -1,0 +1,203 @@
+"""ctypes wrapper around the FP64 CPU oracle (``nurbs_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the package's smoke
+check and by the benchmark's CPU-baseline leg, never by the product path.
+It shares no code with the HIP implementation; inputs come from the seeded
+generators as float32 and are widened here to float64.
+
+Paper passages followed (NURBS-Diff, arXiv 2104.14547): eq. (NURBS) and
+eq. (NURBSBasis) with the indicator eq. (BSplineBasis2) for the forward map
+(Sec. 3.1); eqs. (NURBSuDerivative4), (NURBSvDerivative5),
+(NURBSvDerivative6) and the knot-derivative recursion of Sec. 3.2.1 for the
+backward; eq. (NURBSuDerivative1) of Appendix A for dS/du.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "nurbs_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_lp = ctypes.POINTER(ctypes.c_int64)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc -O2 (no fast-math), OpenMP on."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                               "-Wall", "-Wextra", "-Wno-unused-parameter",
+                               "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(LIB)
+        L.oracle_find_span.restype = ctypes.c_int
+        L.oracle_find_span.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.oracle_basis_dense.restype = ctypes.c_int
+        L.oracle_basis_dense.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         _dp, _dp, _dp]
+        L.oracle_basis_local.restype = ctypes.c_int
+        L.oracle_basis_local.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         _dp, _dp, _dp]
+        L.oracle_max_threads.restype = ctypes.c_int
+        L.oracle_fwd.restype = ctypes.c_int
+        L.oracle_fwd.argtypes = [ctypes.c_int, _ip, _lp] + [_dp] * 9 + [ctypes.c_int, ctypes.c_int]
+        L.oracle_bwd.restype = ctypes.c_int
+        L.oracle_bwd.argtypes = [ctypes.c_int, _ip, _lp] + [_dp] * 11 + [ctypes.c_int, ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _d(x):
+    """float64 contiguous copy + pointer (keeps the array alive via return)."""
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _null():
+    return ctypes.cast(None, _dp)
+
+
+def find_span(U, p: int, u: float) -> int:
+    Ua, Up = _d(U)
+    return int(lib().oracle_find_span(Up, len(Ua), int(p), float(u)))
+
+
+def basis_dense(U, p: int, u: float):
+    """(N[n+1], dN/dU[n+1][len U], dN/du[n+1]) of every degree-p function."""
+    Ua, Up = _d(U)
+    nc = len(Ua) - p - 1
+    N = np.zeros(nc)
+    dU = np.zeros((nc, len(Ua)))
+    du = np.zeros(nc)
+    rc = lib().oracle_basis_dense(Up, len(Ua), int(p), float(u), N.ctypes.data_as(_dp),
+                                  dU.ctypes.data_as(_dp), du.ctypes.data_as(_dp))
+    if rc:
+        raise OracleError(rc)
+    return N, dU, du
+
+
+def basis_local(U, p: int, u: float):
+    """(span k, N[p+1], dN/dU[p+1][2p+2] over knots k-p..k+p+1, dN/du[p+1])."""
+    Ua, Up = _d(U)
+    N = np.zeros(p + 1)
+    dU = np.zeros((p + 1, 2 * p + 2))
+    du = np.zeros(p + 1)
+    k = lib().oracle_basis_local(Up, len(Ua), int(p), float(u), N.ctypes.data_as(_dp),
+                                 dU.ctypes.data_as(_dp), du.ctypes.data_as(_dp))
+    return int(k), N, dU, du
+
+
+def _batch_args(b):
+    shapes = np.ascontiguousarray(b.shapes, np.int32)
+    offs = np.ascontiguousarray(b.offsets, np.int64)
+    keep = [shapes, offs]
+    ptrs = []
+    for name in ("ctrl", "w", "ku", "kv", "us", "vs"):
+        a, p = _d(getattr(b, name))
+        keep.append(a)
+        ptrs.append(p)
+    return keep, shapes.ctypes.data_as(_ip), offs.ctypes.data_as(_lp), ptrs
+
+
+def n_pts_floats(b) -> int:
+    s = np.asarray(b.shapes, np.int64)
+    o = np.asarray(b.offsets, np.int64)
+    if len(s) == 0:
+        return 0
+    return int((o[:, 6] + s[:, 4] * s[:, 5] * 3).max())
+
+
+def fwd(b, local: bool = False, nthreads: int = 0, derivs: bool = False):
+    """Surface points (float64, packed pts layout) of a packed batch ``b``.
+
+    With ``derivs`` also returns dS/du and dS/dv at every sample."""
+    keep, sh, of, ptrs = _batch_args(b)
+    npf = n_pts_floats(b)
+    pts = np.zeros(npf)
+    du = np.zeros(npf) if derivs else None
+    dv = np.zeros(npf) if derivs else None
+    rc = lib().oracle_fwd(len(b.shapes), sh, of, *ptrs, pts.ctypes.data_as(_dp),
+                          du.ctypes.data_as(_dp) if derivs else _null(),
+                          dv.ctypes.data_as(_dp) if derivs else _null(),
+                          int(bool(local)), int(nthreads))
+    del keep
+    if rc:
+        raise OracleError(rc)
+    return (pts, du, dv) if derivs else pts
+
+
+def bwd(b, grad_pts, local: bool = False, nthreads: int = 0):
+    """(dL/dctrl, dL/dw, dL/dku, dL/dkv) in the packed layout, float64."""
+    keep, sh, of, ptrs = _batch_args(b)
+    g, gp = _d(grad_pts)
+    gc = np.zeros(len(b.ctrl))
+    gw = np.zeros(len(b.w))
+    gku = np.zeros(len(b.ku))
+    gkv = np.zeros(len(b.kv))
+    rc = lib().oracle_bwd(len(b.shapes), sh, of, *ptrs, gp, gc.ctypes.data_as(_dp),
+                          gw.ctypes.data_as(_dp), gku.ctypes.data_as(_dp),
+                          gkv.ctypes.data_as(_dp), int(bool(local)), int(nthreads))
+    del keep, g
+    if rc:
+        raise OracleError(rc)
+    return gc, gw, gku, gkv
+
+
+class _One:
+    """A one-surface packed batch built from dense arrays (oracle-side helper)."""
+
+    def __init__(self, ctrl, w, ku, kv, p, q, us, vs):
+        ctrl = np.asarray(ctrl, np.float64)
+        nu_c, nv_c = ctrl.shape[:2]
+        us = np.atleast_1d(np.asarray(us, np.float64))
+        vs = np.atleast_1d(np.asarray(vs, np.float64))
+        self.shapes = np.array([[p, q, nu_c, nv_c, len(us), len(vs)]], np.int32)
+        self.offsets = np.zeros((1, 7), np.int64)
+        self.ctrl = ctrl.ravel()
+        self.w = np.asarray(w, np.float64).ravel()
+        self.ku = np.asarray(ku, np.float64)
+        self.kv = np.asarray(kv, np.float64)
+        self.us, self.vs = us, vs
+        self.dims = (nu_c, nv_c, len(us), len(vs))
+
+
+def surface_fwd(ctrl, w, ku, kv, p, q, us, vs, local=False, derivs=False):
+    """Dense-array convenience: returns S[nu_s][nv_s][3] (and S_u, S_v)."""
+    one = _One(ctrl, w, ku, kv, p, q, us, vs)
+    nu_c, nv_c, nu_s, nv_s = one.dims
+    r = fwd(one, local=local, derivs=derivs)
+    if derivs:
+        return tuple(x.reshape(nu_s, nv_s, 3) for x in r)
+    return r.reshape(nu_s, nv_s, 3)
+
+
+def surface_bwd(ctrl, w, ku, kv, p, q, us, vs, grad_pts, local=False):
+    """Dense-array convenience: returns (dP[nu_c][nv_c][3], dW, dU, dV)."""
+    one = _One(ctrl, w, ku, kv, p, q, us, vs)
+    nu_c, nv_c, nu_s, nv_s = one.dims
+    gc, gw, gku, gkv = bwd(one, np.asarray(grad_pts, np.float64).ravel(), local=local)
+    return gc.reshape(nu_c, nv_c, 3), gw.reshape(nu_c, nv_c), gku, gkv
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())
