@@ -1,0 +1,200 @@
+/*
+ * nurbsdiff.h -- C ABI of libnurbsdiff, batched NURBS surface evaluation and
+ * its adjoint on AMD Instinct MI355X (gfx950).
+ *
+ * The method is NURBS-Diff (arXiv 2104.14547).  The library evaluates
+ *
+ *     S(u,v) = sum_ij N_i^p(u) N_j^q(v) w_ij P_ij / sum_ij N_i^p(u) N_j^q(v) w_ij
+ *
+ * (Sec. 3.1.1, eq. NURBS) on tensor-product parameter grids, with the basis
+ * from the Cox-de Boor recursion (eq. NURBSBasis, eq. BSplineBasis2), only
+ * the p+1 (q+1) non-zero functions of each knot span (Sec. 3.1.2, steps 1-2)
+ * and the homogeneous weighting and rational divide of Sec. 3.1.2 step 3.
+ * The backward is the vector-Jacobian product of Sec. 3.2: dL/dP_ij by the
+ * rational basis (eq. NURBSuDerivative4), dL/dw_ij (eq. NURBSvDerivative5)
+ * and dL/dU_k, dL/dV_k through dS/dN_i (eq. NURBSvDerivative6) and the
+ * knot derivative of the recursion (Sec. 3.2.1).  The Jacobian of
+ * Sec. 3.2.2 is never formed.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All arrays are float32 in device memory unless stated otherwise.  The
+ *    caller owns every buffer, including the workspace; the library never
+ *    allocates on a hot-path call (plans allocate their tables once, at
+ *    creation).  Outputs are fully overwritten, never accumulated.
+ *  - Degrees: 1 <= p, q <= NURBS_MAX_DEGREE; control sides nu_c >= p+1,
+ *    nv_c >= q+1.  Knot vectors have nu_c+p+1 (nv_c+q+1) entries, are
+ *    non-decreasing, and satisfy U_p < U_{p+1} and U_{nu_c-1} < U_{nu_c}.
+ *    Weights are > 0.
+ *  - Knot spans are half-open, U_k <= u < U_{k+1}; a parameter equal to the
+ *    last domain knot U_{nu_c} belongs to span nu_c-1.  Parameters are
+ *    clamped into [U_p, U_{nu_c}] (the clamp carries no gradient).
+ *  - Sample vectors us, vs must be non-decreasing (a tensor-product grid
+ *    in the order it is stored).
+ *  - Layouts (row-major): ctrl [nu_c][nv_c][3], w [nu_c][nv_c],
+ *    ku [nu_c+p+1], kv [nv_c+q+1], us [nu_s], vs [nv_s],
+ *    pts / grad_pts [nu_s][nv_s][3].
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *    stream-ordered and asynchronous; none synchronises the host except
+ *    nurbs_read_device_error.
+ *  - Return codes: NURBS_OK (0) or a negative NURBS_E* code.  Errors that
+ *    the host can detect are returned before anything is launched; the
+ *    message is available from nurbs_last_error().  Data-dependent checks
+ *    (knot order, weight sign, parameter domain, sample order) run on the
+ *    device only with the NURBS_VALIDATE flag; without it such inputs are
+ *    undefined behaviour (parameters outside the domain are clamped).
+ *  - Results are deterministic: no floating-point atomics are used, and a
+ *    surface's result does not depend on the other surfaces of its batch.
+ */
+#ifndef NURBSDIFF_H
+#define NURBSDIFF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NURBS_MAX_DEGREE 7
+
+/* status codes */
+#define NURBS_OK 0
+#define NURBS_EINVAL -1       /* null pointer, bad shape, bad offset */
+#define NURBS_EDEGREE -2      /* p, q outside [1, NURBS_MAX_DEGREE] or nu_c < p+1 */
+#define NURBS_EKNOTS -3       /* (device, VALIDATE) knots decreasing or empty end span */
+#define NURBS_EDOMAIN -4      /* (device, VALIDATE) sample outside the domain or unsorted */
+#define NURBS_EWEIGHTS -5     /* (device, VALIDATE) a weight <= 0 */
+#define NURBS_EWORKSPACE -6   /* workspace missing or too small */
+#define NURBS_EDEVICE -7      /* HIP runtime error (text in nurbs_last_error) */
+#define NURBS_EUNSUPPORTED -8 /* option not supported */
+
+/* gradient selection for the backward */
+#define NURBS_GRAD_CTRL 1u
+#define NURBS_GRAD_W 2u
+#define NURBS_GRAD_KU 4u
+#define NURBS_GRAD_KV 8u
+#define NURBS_GRAD_ALL 15u
+
+/* flags */
+#define NURBS_VALIDATE 1u /* run the device-side data checks */
+
+typedef struct nurbs_ctx nurbs_ctx;
+typedef struct nurbs_plan nurbs_plan;
+
+/* One surface of a ragged batch.  Offsets are element offsets (floats) into
+ * the packed arrays passed to nurbs_plan_fwd / nurbs_plan_bwd.  Gradient
+ * arrays reuse the offsets of the arrays they are gradients of (grad_ctrl at
+ * ctrl_off, grad_w at w_off, grad_ku at ku_off, grad_kv at kv_off, grad_pts
+ * at pts_off). */
+typedef struct {
+    int32_t p, q, nu_c, nv_c, nu_s, nv_s;
+    int64_t ctrl_off, w_off, ku_off, kv_off, us_off, vs_off, pts_off;
+} nurbs_desc;
+
+/* ------------------------------------------------------------------------
+ * Context.  Holds the device ordinal, flags and the last error text.  Not
+ * thread-safe: one context per host thread.
+ *   device : HIP device ordinal the calls run on (must be current).
+ *   out    : receives the new context; release with nurbs_ctx_destroy.
+ * ---------------------------------------------------------------------- */
+int nurbs_ctx_create(int device, nurbs_ctx **out);
+int nurbs_ctx_destroy(nurbs_ctx *ctx);
+/* flags: NURBS_VALIDATE or 0; applies to the uniform-batch calls. */
+int nurbs_ctx_set_flags(nurbs_ctx *ctx, unsigned flags);
+/* Bandwidth of the Gaussian that smooths the degree-0 indicator's knot
+ * derivative (Sec. 3.2.1).  Only sigma == 0, the zero-bandwidth limit in
+ * which knot gradients are the exact derivative of the piecewise-polynomial
+ * basis, is supported; any other value returns NURBS_EUNSUPPORTED. */
+int nurbs_ctx_set_knot_sigma(nurbs_ctx *ctx, float sigma);
+const char *nurbs_status_string(int status);
+/* Text of the last error raised on this context (never NULL). */
+const char *nurbs_last_error(nurbs_ctx *ctx);
+/* Number of compute units of the context's device (for callers sizing work). */
+int nurbs_ctx_device_info(nurbs_ctx *ctx, int *num_cus, int *wave_size);
+
+/* ------------------------------------------------------------------------
+ * Uniform batch: B surfaces of identical shape -- the paper's call
+ * surface(ctrl, weights, knot_u, knot_v, p, q, uv) -> points (Sec. 3.1,
+ * Alg. Forward; Sec. 3.2, Alg. Backward).
+ *   ctrl [B][nu_c][nv_c][3], w [B][nu_c][nv_c], ku [B][nu_c+p+1],
+ *   kv [B][nv_c+q+1]; us [nu_s], vs [nv_s] if uv_shared != 0 else
+ *   us [B][nu_s], vs [B][nv_s]; pts [B][nu_s][nv_s][3].
+ *   ws / ws_bytes : caller-owned device workspace of at least the size
+ *   reported by nurbs_surface_ws_bytes (with the same shapes and mask);
+ *   may be NULL when that size is 0.
+ * ---------------------------------------------------------------------- */
+int nurbs_surface_ws_bytes(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
+                           int nu_s, int nv_s, unsigned grad_mask, size_t *out);
+
+int nurbs_surface_fwd(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
+                      const float *ctrl, const float *w, const float *ku,
+                      const float *kv, int nu_s, int nv_s, const float *us,
+                      const float *vs, int uv_shared, float *pts, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* Vector-Jacobian product.  grad_pts = dL/dS [B][nu_s][nv_s][3].  Outputs
+ * (each overwritten when its grad_mask bit is set, untouched and allowed to
+ * be NULL otherwise): grad_ctrl [B][nu_c][nv_c][3], grad_w [B][nu_c][nv_c],
+ * grad_ku [B][nu_c+p+1], grad_kv [B][nv_c+q+1].  No gradient is returned
+ * for the parameters us, vs (the paper's module does not use dS/du). */
+int nurbs_surface_bwd(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
+                      const float *ctrl, const float *w, const float *ku,
+                      const float *kv, int nu_s, int nv_s, const float *us,
+                      const float *vs, int uv_shared, const float *grad_pts,
+                      float *grad_ctrl, float *grad_w, float *grad_ku,
+                      float *grad_kv, unsigned grad_mask, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Ragged batch ("plan"): thousands of surfaces of uneven degree, control
+ * grid and sample grid in one persistent launch per direction (the paper's
+ * batched forward of Alg. Forward over all surfaces, and Alg. Backward).
+ *   host     : n descriptors in host memory (copied; may be freed after).
+ *   flags    : NURBS_VALIDATE or 0.
+ *   out      : receives the plan (owns its device tables).
+ *   ws_bytes : receives the workspace size the plan's calls need.
+ * The plan is bound to the device current at creation.  nurbs_plan_fwd /
+ * nurbs_plan_bwd take packed arrays laid out as the descriptors say, launch
+ * without host synchronisation or allocation, and may be captured in a HIP
+ * graph.  Two calls of one plan must not run concurrently (they share the
+ * plan's work counters); use one plan per stream.
+ * ---------------------------------------------------------------------- */
+int nurbs_plan_create(nurbs_ctx *ctx, const nurbs_desc *host, int n, unsigned flags,
+                      nurbs_plan **out, size_t *ws_bytes);
+int nurbs_plan_destroy(nurbs_plan *plan);
+/* Tile statistics of a plan: number of forward / backward tiles. */
+int nurbs_plan_info(nurbs_plan *plan, int *fwd_tiles, int *bwd_tiles, int *grid);
+
+int nurbs_plan_fwd(nurbs_plan *plan, const float *ctrl, const float *w,
+                   const float *ku, const float *kv, const float *us,
+                   const float *vs, float *pts, void *ws, size_t ws_bytes,
+                   void *stream);
+
+int nurbs_plan_bwd(nurbs_plan *plan, const float *ctrl, const float *w,
+                   const float *ku, const float *kv, const float *us,
+                   const float *vs, const float *grad_pts, float *grad_ctrl,
+                   float *grad_w, float *grad_ku, float *grad_kv,
+                   unsigned grad_mask, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Test exports: the device span search and basis used by the kernels.
+ *   knots [n_knots] (device), x [nx] (device); p in [1, NURBS_MAX_DEGREE].
+ *   spans [nx] int32 (device): k with U_k <= x < U_{k+1} (Sec. 3.1.2 step 1,
+ *   half-open, last span closed; x clamped into the domain).
+ *   N [nx][p+1] (device): N_{k-p..k}^p(x) (eq. NURBSBasis).
+ * ---------------------------------------------------------------------- */
+int nurbs_find_spans(const float *knots, int n_knots, int p, const float *x, int nx,
+                     int32_t *spans, void *stream);
+int nurbs_basis(const float *knots, int n_knots, int p, const float *x, int nx,
+                float *N, void *stream);
+
+/* Synchronises `stream`, reads the first data error recorded by a
+ * NURBS_VALIDATE call into its workspace `ws`, stores it in *code
+ * (NURBS_OK if none) and clears it. */
+int nurbs_read_device_error(const void *ws, void *stream, int *code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NURBSDIFF_H */

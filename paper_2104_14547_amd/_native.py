@@ -1,0 +1,106 @@
+"""ctypes binding of libnurbsdiff (include/nurbsdiff.h): argument marshalling only.
+
+Every entry point keeps the C name.  Pointers are raw device addresses
+(``tensor.data_ptr()``) and streams raw ``hipStream_t`` handles.  The library
+is loaded from this package directory; if it is missing the import fails
+loudly -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnurbsdiff.so")
+
+NURBS_OK = 0
+NURBS_EINVAL = -1
+NURBS_EDEGREE = -2
+NURBS_EKNOTS = -3
+NURBS_EDOMAIN = -4
+NURBS_EWEIGHTS = -5
+NURBS_EWORKSPACE = -6
+NURBS_EDEVICE = -7
+NURBS_EUNSUPPORTED = -8
+
+NURBS_GRAD_CTRL = 1
+NURBS_GRAD_W = 2
+NURBS_GRAD_KU = 4
+NURBS_GRAD_KV = 8
+NURBS_GRAD_ALL = 15
+NURBS_VALIDATE = 1
+NURBS_MAX_DEGREE = 7
+
+# every symbol include/nurbsdiff.h declares
+EXPORTS = (
+    "nurbs_ctx_create", "nurbs_ctx_destroy", "nurbs_ctx_set_flags", "nurbs_ctx_set_knot_sigma",
+    "nurbs_status_string", "nurbs_last_error", "nurbs_ctx_device_info",
+    "nurbs_surface_ws_bytes", "nurbs_surface_fwd", "nurbs_surface_bwd",
+    "nurbs_plan_create", "nurbs_plan_destroy", "nurbs_plan_info", "nurbs_plan_fwd", "nurbs_plan_bwd",
+    "nurbs_find_spans", "nurbs_basis", "nurbs_read_device_error",
+)
+
+
+class nurbs_desc(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("p", "q", "nu_c", "nv_c", "nu_s", "nv_s")] + \
+               [(n, ctypes.c_int64) for n in ("ctrl_off", "w_off", "ku_off", "kv_off", "us_off",
+                                              "vs_off", "pts_off")]
+
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_u = ctypes.c_uint
+_sz = ctypes.c_size_t
+_szp = ctypes.POINTER(ctypes.c_size_t)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+_SIGS = {
+    "nurbs_ctx_create": (_i, [_i, ctypes.POINTER(_vp)]),
+    "nurbs_ctx_destroy": (_i, [_vp]),
+    "nurbs_ctx_set_flags": (_i, [_vp, _u]),
+    "nurbs_ctx_set_knot_sigma": (_i, [_vp, ctypes.c_float]),
+    "nurbs_status_string": (ctypes.c_char_p, [_i]),
+    "nurbs_last_error": (ctypes.c_char_p, [_vp]),
+    "nurbs_ctx_device_info": (_i, [_vp, _ip, _ip]),
+    "nurbs_surface_ws_bytes": (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, _u, _szp]),
+    "nurbs_surface_fwd": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _i, _vp,
+                               _vp, _sz, _vp]),
+    "nurbs_surface_bwd": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _i, _vp,
+                               _vp, _vp, _vp, _vp, _u, _vp, _sz, _vp]),
+    "nurbs_plan_create": (_i, [_vp, ctypes.POINTER(nurbs_desc), _i, _u, ctypes.POINTER(_vp), _szp]),
+    "nurbs_plan_destroy": (_i, [_vp]),
+    "nurbs_plan_info": (_i, [_vp, _ip, _ip, _ip]),
+    "nurbs_plan_fwd": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "nurbs_plan_bwd": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u, _vp, _sz,
+                            _vp]),
+    "nurbs_find_spans": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp]),
+    "nurbs_basis": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp]),
+    "nurbs_read_device_error": (_i, [_vp, _vp, _ip]),
+}
+
+_lib = None
+
+
+class NativeLibraryMissing(ImportError):
+    pass
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise NativeLibraryMissing(
+                f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().nurbs_status_string(int(code)).decode()

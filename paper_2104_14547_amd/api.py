@@ -1,0 +1,340 @@
+"""PyTorch-facing API over libnurbsdiff.
+
+PyTorch supplies device memory and streams; every step of the computation
+runs in the library's HIP kernels.  Shapes follow the paper's statement of the
+problem, surface(ctrl_pts, weights, knot_u, knot_v, p, q, uv) -> points
+(Sec. 3.1, eq. ForwardEvaluation), and its backward (Sec. 3.2).
+"""
+from __future__ import annotations
+
+import ctypes
+import threading
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+
+class NurbsError(RuntimeError):
+    """A non-zero status from libnurbsdiff."""
+
+    def __init__(self, code: int, message: str):
+        self.code = int(code)
+        super().__init__(f"{N.status_string(code)} ({code}): {message}")
+
+
+def _check(rc: int, ctx_handle=None):
+    if rc != N.NURBS_OK:
+        msg = N.lib().nurbs_last_error(ctx_handle).decode()
+        raise NurbsError(rc, msg)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _need_cuda_f32(name, t):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+
+
+class Context:
+    """One libnurbsdiff context (device ordinal, flags, last error)."""
+
+    def __init__(self, device: int | None = None, validate: bool = False):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        _check(N.lib().nurbs_ctx_create(self.device, ctypes.byref(h)))
+        self.handle = h
+        self.flags = 0
+        if validate:
+            self.set_flags(N.NURBS_VALIDATE)
+
+    def set_flags(self, flags: int):
+        _check(N.lib().nurbs_ctx_set_flags(self.handle, int(flags)), self.handle)
+        self.flags = int(flags)
+
+    @property
+    def validate(self) -> bool:
+        return bool(self.flags & N.NURBS_VALIDATE)
+
+    def read_device_error(self, ws, device=None) -> int:
+        code = ctypes.c_int()
+        _check(N.lib().nurbs_read_device_error(_ptr(ws), _stream(ws.device), ctypes.byref(code)))
+        return code.value
+
+    def set_knot_sigma(self, sigma: float):
+        _check(N.lib().nurbs_ctx_set_knot_sigma(self.handle, float(sigma)), self.handle)
+
+    def device_info(self):
+        cus, wave = ctypes.c_int(), ctypes.c_int()
+        _check(N.lib().nurbs_ctx_device_info(self.handle, ctypes.byref(cus), ctypes.byref(wave)), self.handle)
+        return cus.value, wave.value
+
+    def close(self):
+        if self.handle:
+            N.lib().nurbs_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_tls = threading.local()
+
+
+def context(device: int | None = None) -> Context:
+    """The calling thread's default context for ``device``."""
+    if device is None:
+        device = torch.cuda.current_device()
+    cache = getattr(_tls, "ctx", None)
+    if cache is None:
+        cache = _tls.ctx = {}
+    c = cache.get(device)
+    if c is None:
+        c = cache[device] = Context(device)
+    return c
+
+
+def _uniform_shapes(ctrl, w, ku, kv, p, q, us, vs):
+    _need_cuda_f32("ctrl", ctrl)
+    for name, t in (("w", w), ("ku", ku), ("kv", kv), ("us", us), ("vs", vs)):
+        _need_cuda_f32(name, t)
+    if ctrl.dim() == 3:
+        ctrl, w, ku, kv = ctrl[None], w[None], ku[None], kv[None]
+    if ctrl.dim() != 4 or ctrl.shape[-1] != 3:
+        raise ValueError("ctrl must be [B, nu_c, nv_c, 3] or [nu_c, nv_c, 3]")
+    B, nu_c, nv_c = (int(x) for x in ctrl.shape[:3])
+    if tuple(w.shape) != (B, nu_c, nv_c):
+        raise ValueError("w must be [B, nu_c, nv_c]")
+    if tuple(ku.shape) != (B, nu_c + p + 1) or tuple(kv.shape) != (B, nv_c + q + 1):
+        raise ValueError("knot vectors must be [B, nu_c+p+1] and [B, nv_c+q+1]")
+    if us.dim() == 1 and vs.dim() == 1:
+        shared = 1
+        nu_s, nv_s = int(us.shape[0]), int(vs.shape[0])
+    elif us.dim() == 2 and vs.dim() == 2 and us.shape[0] == B and vs.shape[0] == B:
+        shared = 0
+        nu_s, nv_s = int(us.shape[1]), int(vs.shape[1])
+    else:
+        raise ValueError("us, vs must both be [n] (shared) or both be [B, n]")
+    return ctrl, w, ku, kv, B, nu_c, nv_c, nu_s, nv_s, shared
+
+
+def surface_fwd(ctrl, w, ku, kv, p: int, q: int, us, vs, out=None, ctx: Context | None = None):
+    """Points S[B, nu_s, nv_s, 3] of a uniform batch (nurbs_surface_fwd)."""
+    squeeze = ctrl.dim() == 3
+    ctrl, w, ku, kv, B, nu_c, nv_c, nu_s, nv_s, shared = _uniform_shapes(ctrl, w, ku, kv, p, q, us, vs)
+    ctx = ctx or context(ctrl.device.index)
+    if out is None:
+        out = torch.empty((B, nu_s, nv_s, 3), dtype=torch.float32, device=ctrl.device)
+    ws_n = ctypes.c_size_t()
+    _check(N.lib().nurbs_surface_ws_bytes(ctx.handle, B, p, q, nu_c, nv_c, nu_s, nv_s, 0,
+                                          ctypes.byref(ws_n)), ctx.handle)
+    ws = torch.zeros(ws_n.value, dtype=torch.uint8, device=ctrl.device) if ws_n.value else None
+    ctx.last_ws = ws
+    _check(N.lib().nurbs_surface_fwd(ctx.handle, B, p, q, nu_c, nv_c, _ptr(ctrl), _ptr(w), _ptr(ku), _ptr(kv),
+                                     nu_s, nv_s, _ptr(us), _ptr(vs), shared, _ptr(out), _ptr(ws), ws_n.value,
+                                     _stream(ctrl.device)), ctx.handle)
+    return out[0] if squeeze else out
+
+
+def surface_bwd(ctrl, w, ku, kv, p: int, q: int, us, vs, grad_pts, mask: int = N.NURBS_GRAD_ALL,
+                ctx: Context | None = None):
+    """(dL/dctrl, dL/dw, dL/dku, dL/dkv) of a uniform batch (nurbs_surface_bwd).
+    Entries whose mask bit is clear are None."""
+    squeeze = ctrl.dim() == 3
+    ctrl, w, ku, kv, B, nu_c, nv_c, nu_s, nv_s, shared = _uniform_shapes(ctrl, w, ku, kv, p, q, us, vs)
+    grad_pts = grad_pts.contiguous()
+    if squeeze:
+        grad_pts = grad_pts[None]
+    _need_cuda_f32("grad_pts", grad_pts)
+    if tuple(grad_pts.shape) != (B, nu_s, nv_s, 3):
+        raise ValueError("grad_pts must be [B, nu_s, nv_s, 3]")
+    ctx = ctx or context(ctrl.device.index)
+    dev = ctrl.device
+    gc = torch.empty_like(ctrl) if mask & N.NURBS_GRAD_CTRL else None
+    gw = torch.empty_like(w) if mask & N.NURBS_GRAD_W else None
+    gu = torch.empty_like(ku) if mask & N.NURBS_GRAD_KU else None
+    gv = torch.empty_like(kv) if mask & N.NURBS_GRAD_KV else None
+    ws_n = ctypes.c_size_t()
+    _check(N.lib().nurbs_surface_ws_bytes(ctx.handle, B, p, q, nu_c, nv_c, nu_s, nv_s, mask,
+                                          ctypes.byref(ws_n)), ctx.handle)
+    ws = torch.empty(ws_n.value, dtype=torch.uint8, device=dev) if ws_n.value else None
+    if ws is not None and ctx.validate:
+        ws[:256].zero_()
+    ctx.last_ws = ws
+    _check(N.lib().nurbs_surface_bwd(ctx.handle, B, p, q, nu_c, nv_c, _ptr(ctrl), _ptr(w), _ptr(ku), _ptr(kv),
+                                     nu_s, nv_s, _ptr(us), _ptr(vs), shared, _ptr(grad_pts), _ptr(gc), _ptr(gw),
+                                     _ptr(gu), _ptr(gv), int(mask), _ptr(ws), ws_n.value, _stream(dev)),
+           ctx.handle)
+    res = (gc, gw, gu, gv)
+    if squeeze:
+        res = tuple(None if r is None else r[0] for r in res)
+    return res
+
+
+class NurbsSurfaceFn(torch.autograd.Function):
+    """Differentiable uniform-batch evaluation; the backward is the library's
+    hand-written adjoint (no autograd tape through the kernels)."""
+
+    @staticmethod
+    def forward(fctx, ctrl, w, ku, kv, p, q, us, vs):
+        pts = surface_fwd(ctrl, w, ku, kv, p, q, us, vs)
+        fctx.save_for_backward(ctrl, w, ku, kv, us, vs)
+        fctx.pq = (p, q)
+        return pts
+
+    @staticmethod
+    def backward(fctx, grad_pts):
+        ctrl, w, ku, kv, us, vs = fctx.saved_tensors
+        p, q = fctx.pq
+        need = fctx.needs_input_grad
+        mask = (N.NURBS_GRAD_CTRL if need[0] else 0) | (N.NURBS_GRAD_W if need[1] else 0) | \
+               (N.NURBS_GRAD_KU if need[2] else 0) | (N.NURBS_GRAD_KV if need[3] else 0)
+        if mask == 0:
+            return (None,) * 8
+        gc, gw, gu, gv = surface_bwd(ctrl, w, ku, kv, p, q, us, vs, grad_pts.contiguous(), mask)
+        return gc, gw, gu, gv, None, None, None, None
+
+
+def surface(ctrl, w, ku, kv, p: int, q: int, us, vs):
+    """S = surface(ctrl, w, ku, kv, p, q, us, vs), differentiable in ctrl, w,
+    ku and kv (the parameters us, vs get no gradient)."""
+    return NurbsSurfaceFn.apply(ctrl.contiguous(), w.contiguous(), ku.contiguous(), kv.contiguous(),
+                                int(p), int(q), us.contiguous(), vs.contiguous())
+
+
+class NurbsSurface(torch.nn.Module):
+    """A batch of B surfaces of one shape as trainable parameters."""
+
+    def __init__(self, ctrl, w, ku, kv, p: int, q: int, train_knots: bool = True):
+        super().__init__()
+        self.p, self.q = int(p), int(q)
+        self.ctrl = torch.nn.Parameter(ctrl.detach().clone().contiguous())
+        self.w = torch.nn.Parameter(w.detach().clone().contiguous())
+        self.ku = torch.nn.Parameter(ku.detach().clone().contiguous(), requires_grad=train_knots)
+        self.kv = torch.nn.Parameter(kv.detach().clone().contiguous(), requires_grad=train_knots)
+
+    def forward(self, us, vs):
+        return surface(self.ctrl, self.w, self.ku, self.kv, self.p, self.q, us, vs)
+
+
+# --------------------------------------------------------------------------
+# ragged batches
+# --------------------------------------------------------------------------
+
+class SurfaceBatch:
+    """A ragged batch plan (nurbs_plan_*): surfaces of uneven degree, control
+    grid and sample grid, one persistent launch per direction.
+
+    ``shapes`` int [n][6] = (p, q, nu_c, nv_c, nu_s, nv_s); ``offsets`` int
+    [n][7] element offsets of (ctrl, w, ku, kv, us, vs, pts) in the packed
+    arrays passed to ``forward`` / ``backward``."""
+
+    def __init__(self, shapes, offsets, device: int | None = None, validate: bool = False,
+                 ctx: Context | None = None):
+        shapes = np.ascontiguousarray(shapes, np.int64)
+        offsets = np.ascontiguousarray(offsets, np.int64)
+        n = int(shapes.shape[0])
+        self.n = n
+        self.ctx = ctx or context(device)
+        self.device = torch.device("cuda", self.ctx.device)
+        arr = (N.nurbs_desc * max(n, 1))()
+        for s in range(n):
+            d = arr[s]
+            d.p, d.q, d.nu_c, d.nv_c, d.nu_s, d.nv_s = (int(x) for x in shapes[s])
+            (d.ctrl_off, d.w_off, d.ku_off, d.kv_off, d.us_off, d.vs_off, d.pts_off) = (int(x) for x in offsets[s])
+        h = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        flags = N.NURBS_VALIDATE if validate else 0
+        _check(N.lib().nurbs_plan_create(self.ctx.handle, arr, n, flags, ctypes.byref(h), ctypes.byref(ws)),
+               self.ctx.handle)
+        self.handle = h
+        self.ws_bytes = ws.value
+        self.validate = validate
+        self.shapes, self.offsets = shapes, offsets
+        s = shapes
+        self.n_pts_floats = int((offsets[:, 6] + s[:, 4] * s[:, 5] * 3).max()) if n else 0
+        self.n_points = int((s[:, 4] * s[:, 5]).sum()) if n else 0
+        self._ws = None
+
+    def info(self):
+        f, b, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(N.lib().nurbs_plan_info(self.handle, ctypes.byref(f), ctypes.byref(b), ctypes.byref(g)))
+        return {"fwd_tiles": f.value, "bwd_tiles": b.value, "grid": g.value}
+
+    def workspace(self):
+        """The plan's workspace (allocated once, reused by every call)."""
+        if self._ws is None:
+            self._ws = torch.zeros(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def forward(self, ctrl, w, ku, kv, us, vs, out=None, stream=None):
+        if out is None:
+            out = torch.empty(self.n_pts_floats, dtype=torch.float32, device=self.device)
+        ws = self.workspace()
+        st = stream.cuda_stream if stream is not None else _stream(self.device)
+        _check(N.lib().nurbs_plan_fwd(self.handle, _ptr(ctrl), _ptr(w), _ptr(ku), _ptr(kv), _ptr(us), _ptr(vs),
+                                      _ptr(out), _ptr(ws), ws.numel(), st), self.ctx.handle)
+        return out
+
+    def backward(self, ctrl, w, ku, kv, us, vs, grad_pts, mask: int = N.NURBS_GRAD_ALL, out=None, stream=None):
+        if out is None:
+            out = (torch.empty_like(ctrl) if mask & 1 else None, torch.empty_like(w) if mask & 2 else None,
+                   torch.empty_like(ku) if mask & 4 else None, torch.empty_like(kv) if mask & 8 else None)
+        gc, gw, gu, gv = out
+        ws = self.workspace()
+        st = stream.cuda_stream if stream is not None else _stream(self.device)
+        _check(N.lib().nurbs_plan_bwd(self.handle, _ptr(ctrl), _ptr(w), _ptr(ku), _ptr(kv), _ptr(us), _ptr(vs),
+                                      _ptr(grad_pts), _ptr(gc), _ptr(gw), _ptr(gu), _ptr(gv), int(mask), _ptr(ws),
+                                      ws.numel(), st), self.ctx.handle)
+        return out
+
+    def read_device_error(self, stream=None) -> int:
+        code = ctypes.c_int()
+        st = stream.cuda_stream if stream is not None else _stream(self.device)
+        _check(N.lib().nurbs_read_device_error(_ptr(self.workspace()), st, ctypes.byref(code)))
+        return code.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            N.lib().nurbs_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------------------
+# test exports
+# --------------------------------------------------------------------------
+
+def find_spans(knots, p: int, x):
+    _need_cuda_f32("knots", knots)
+    _need_cuda_f32("x", x)
+    out = torch.empty(x.numel(), dtype=torch.int32, device=x.device)
+    _check(N.lib().nurbs_find_spans(_ptr(knots), knots.numel(), int(p), _ptr(x), x.numel(), _ptr(out),
+                                    _stream(x.device)))
+    return out
+
+
+def basis(knots, p: int, x):
+    _need_cuda_f32("knots", knots)
+    _need_cuda_f32("x", x)
+    out = torch.empty((x.numel(), p + 1), dtype=torch.float32, device=x.device)
+    _check(N.lib().nurbs_basis(_ptr(knots), knots.numel(), int(p), _ptr(x), x.numel(), _ptr(out),
+                               _stream(x.device)))
+    return out

@@ -1,0 +1,534 @@
+// libnurbsdiff host side: the C ABI of include/nurbsdiff.h.  Validates
+// arguments, builds tilings and ragged-batch plans, and launches the kernels
+// of the k_*.hip translation units on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/nurbsdiff.h"
+#include "kernels.hpp"
+#include "launch.hpp"
+
+using namespace nd;
+
+struct nurbs_ctx {
+    int device = 0;
+    unsigned flags = 0;
+    int num_cus = 0;
+    std::string err;
+};
+
+struct nurbs_plan {
+    nurbs_ctx* ctx = nullptr;
+    int device = 0;
+    int n = 0;
+    unsigned flags = 0;
+    std::vector<nurbs_desc> host;
+    // device tables (one allocation)
+    void* dev = nullptr;
+    DevDesc* d_desc = nullptr;
+    DevTile* d_ftiles = nullptr;
+    int* d_forder = nullptr;
+    DevTile* d_btiles = nullptr;
+    int* d_border = nullptr;
+    unsigned* d_counters = nullptr;  // fwd pair, bwd pair
+    int nf = 0, nb = 0;
+    int grid_fwd = 0, grid_bwd = 0;
+    size_t ws_bytes = 0;
+    int max_nU = 0, max_nV = 0;
+    int maxd = 5;  // degree class of the persistent kernels (5 or 7)
+};
+
+namespace {
+
+thread_local std::string g_noctx_err;
+
+int fail(nurbs_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg; else g_noctx_err = msg;
+    return code;
+}
+
+int hip_fail(nurbs_ctx* c, hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c, NURBS_EDEVICE, m);
+}
+
+int check_shape(nurbs_ctx* c, int p, int q, int nu_c, int nv_c, int nu_s, int nv_s) {
+    if (p < 1 || q < 1 || p > NURBS_MAX_DEGREE || q > NURBS_MAX_DEGREE)
+        return fail(c, NURBS_EDEGREE, "degree outside [1, " + std::to_string(NURBS_MAX_DEGREE) + "]");
+    if (nu_c < p + 1 || nv_c < q + 1) return fail(c, NURBS_EDEGREE, "fewer control points than degree+1");
+    if (nu_s < 0 || nv_s < 0) return fail(c, NURBS_EINVAL, "negative sample count");
+    if ((long long)nu_c * nv_c > (1ll << 26)) return fail(c, NURBS_EINVAL, "control grid too large");
+    if (nu_c + p + 1 > kWG || nv_c + q + 1 > kWG)
+        return fail(c, NURBS_EINVAL, "knot vector longer than " + std::to_string(kWG));
+    return NURBS_OK;
+}
+
+// Rows per tile from the surface's own shape only, so that a surface gets
+// the same tiling -- and bitwise the same result -- alone, in a uniform
+// batch or in any ragged mix.  A tile is one wave64 over min(64, nv_s)
+// columns; the row count aims at a fixed number of points per tile.
+constexpr int kFwdTilePts = 4096;
+constexpr int kBwdTilePts = 8192;
+int tile_rows(int nu_s, int nv_s, int target_pts) {
+    const int cols = std::max(1, std::min(kWave, nv_s));
+    const int rows = std::max(1, target_pts / cols);
+    return std::max(1, std::min(std::max(nu_s, 1), rows));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nurbs_status_string(int s) {
+    switch (s) {
+        case NURBS_OK: return "ok";
+        case NURBS_EINVAL: return "invalid argument";
+        case NURBS_EDEGREE: return "unsupported degree or too few control points";
+        case NURBS_EKNOTS: return "invalid knot vector";
+        case NURBS_EDOMAIN: return "sample outside the domain or unsorted";
+        case NURBS_EWEIGHTS: return "non-positive weight";
+        case NURBS_EWORKSPACE: return "workspace missing or too small";
+        case NURBS_EDEVICE: return "HIP runtime error";
+        case NURBS_EUNSUPPORTED: return "unsupported option";
+        default: return "unknown status";
+    }
+}
+
+int nurbs_ctx_create(int device, nurbs_ctx** out) {
+    if (!out) return fail(nullptr, NURBS_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(nullptr, NURBS_EINVAL, "no such device");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceProperties");
+    nurbs_ctx* c = new nurbs_ctx();
+    c->device = device;
+    c->num_cus = prop.multiProcessorCount;
+    *out = c;
+    return NURBS_OK;
+}
+
+int nurbs_ctx_destroy(nurbs_ctx* ctx) {
+    delete ctx;
+    return NURBS_OK;
+}
+
+int nurbs_ctx_set_flags(nurbs_ctx* ctx, unsigned flags) {
+    if (!ctx) return fail(nullptr, NURBS_EINVAL, "ctx is NULL");
+    if (flags & ~NURBS_VALIDATE) return fail(ctx, NURBS_EINVAL, "unknown flag bits");
+    ctx->flags = flags;
+    return NURBS_OK;
+}
+
+int nurbs_ctx_set_knot_sigma(nurbs_ctx* ctx, float sigma) {
+    if (!ctx) return fail(nullptr, NURBS_EINVAL, "ctx is NULL");
+    if (sigma != 0.0f)
+        return fail(ctx, NURBS_EUNSUPPORTED, "only the zero-bandwidth knot derivative (sigma = 0) is supported");
+    return NURBS_OK;
+}
+
+const char* nurbs_last_error(nurbs_ctx* ctx) { return ctx ? ctx->err.c_str() : g_noctx_err.c_str(); }
+
+int nurbs_ctx_device_info(nurbs_ctx* ctx, int* num_cus, int* wave_size) {
+    if (!ctx) return fail(nullptr, NURBS_EINVAL, "ctx is NULL");
+    if (num_cus) *num_cus = ctx->num_cus;
+    if (wave_size) *wave_size = kWave;
+    return NURBS_OK;
+}
+
+// --------------------------------------------------------------------------
+// uniform batch
+// --------------------------------------------------------------------------
+namespace {
+
+struct UniformGeom {
+    int ncb, nrb_f, rows_f, nrb_b, rows_b;
+    long long tiles_f, tiles_b;
+    size_t slot;
+};
+
+UniformGeom uniform_geom(const nurbs_ctx* c, int B, int p, int q, int nu_c, int nv_c, int nu_s, int nv_s) {
+    UniformGeom g;
+    g.ncb = (nv_s + kWave - 1) / kWave;
+    const long long cols = (long long)B * g.ncb;
+    g.rows_f = tile_rows(nu_s, nv_s, kFwdTilePts);
+    g.rows_b = tile_rows(nu_s, nv_s, kBwdTilePts);
+    g.nrb_f = (nu_s + g.rows_f - 1) / g.rows_f;
+    g.nrb_b = (nu_s + g.rows_b - 1) / g.rows_b;
+    g.tiles_f = cols * g.nrb_f;
+    g.tiles_b = cols * g.nrb_b;
+    g.slot = slot_bytes(p, q, nu_c, nv_c, g.rows_b);
+    return g;
+}
+
+constexpr size_t kWsHeader = 256;  // error word + padding
+
+int uniform_common(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, int nu_s, int nv_s) {
+    if (!ctx) return fail(nullptr, NURBS_EINVAL, "ctx is NULL");
+    if (B < 0) return fail(ctx, NURBS_EINVAL, "negative batch");
+    return check_shape(ctx, p, q, nu_c, nv_c, nu_s, nv_s);
+}
+
+UniformArgs make_uargs(const nurbs_ctx* ctx, const UniformGeom& g, bool bwd, int B, int nu_c, int nv_c,
+                       int nu_s, int nv_s, const float* ctrl, const float* w, const float* ku,
+                       const float* kv, const float* us, const float* vs, int uv_shared, void* ws) {
+    UniformArgs a;
+    a.ctrl = ctrl; a.w = w; a.ku = ku; a.kv = kv; a.us = us; a.vs = vs;
+    a.B = B; a.nu_c = nu_c; a.nv_c = nv_c; a.nu_s = nu_s; a.nv_s = nv_s; a.uv_shared = uv_shared ? 1 : 0;
+    a.ncb = g.ncb;
+    a.nrb = bwd ? g.nrb_b : g.nrb_f;
+    a.rows = bwd ? g.rows_b : g.rows_f;
+    a.ntiles = (int)(bwd ? g.tiles_b : g.tiles_f);
+    a.flags = ctx->flags;
+    a.err = (ctx->flags & NURBS_VALIDATE) ? reinterpret_cast<int*>(ws) : nullptr;
+    return a;
+}
+
+}  // namespace
+
+int nurbs_surface_ws_bytes(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, int nu_s, int nv_s,
+                           unsigned grad_mask, size_t* out) {
+    int rc = uniform_common(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
+    if (rc) return rc;
+    if (!out) return fail(ctx, NURBS_EINVAL, "out is NULL");
+    if (grad_mask & ~NURBS_GRAD_ALL) return fail(ctx, NURBS_EINVAL, "unknown gradient bits");
+    if (grad_mask == 0) {
+        *out = (ctx->flags & NURBS_VALIDATE) ? kWsHeader : 0;
+        return NURBS_OK;
+    }
+    const UniformGeom g = uniform_geom(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
+    *out = kWsHeader + (size_t)g.tiles_b * g.slot;
+    return NURBS_OK;
+}
+
+int nurbs_surface_fwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, const float* ctrl,
+                      const float* w, const float* ku, const float* kv, int nu_s, int nv_s, const float* us,
+                      const float* vs, int uv_shared, float* pts, void* ws, size_t ws_bytes, void* stream) {
+    int rc = uniform_common(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
+    if (rc) return rc;
+    if (B == 0 || nu_s == 0 || nv_s == 0) return NURBS_OK;
+    if (!ctrl || !w || !ku || !kv || !us || !vs || !pts) return fail(ctx, NURBS_EINVAL, "NULL array");
+    if ((ctx->flags & NURBS_VALIDATE) && (!ws || ws_bytes < kWsHeader))
+        return fail(ctx, NURBS_EWORKSPACE, "NURBS_VALIDATE needs a workspace");
+    const UniformGeom g = uniform_geom(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
+    if (g.tiles_f > (1ll << 30)) return fail(ctx, NURBS_EINVAL, "batch too large");
+    UniformArgs a = make_uargs(ctx, g, false, B, nu_c, nv_c, nu_s, nv_s, ctrl, w, ku, kv, us, vs, uv_shared, ws);
+    const dim3 grid((unsigned)((g.tiles_f + kWavesPerWG - 1) / kWavesPerWG));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipErrorInvalidValue;
+    switch (p) {
+#define ND_CASE(P) case P: e = launch_uniform_fwd_p##P(q, grid, st, a, pts); break;
+        ND_CASE(1) ND_CASE(2) ND_CASE(3) ND_CASE(4) ND_CASE(5) ND_CASE(6) ND_CASE(7)
+#undef ND_CASE
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "launch forward");
+    return NURBS_OK;
+}
+
+int nurbs_surface_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, const float* ctrl,
+                      const float* w, const float* ku, const float* kv, int nu_s, int nv_s, const float* us,
+                      const float* vs, int uv_shared, const float* grad_pts, float* grad_ctrl, float* grad_w,
+                      float* grad_ku, float* grad_kv, unsigned grad_mask, void* ws, size_t ws_bytes,
+                      void* stream) {
+    int rc = uniform_common(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
+    if (rc) return rc;
+    if (grad_mask & ~NURBS_GRAD_ALL) return fail(ctx, NURBS_EINVAL, "unknown gradient bits");
+    if (grad_mask == 0 || B == 0) return NURBS_OK;
+    if (((grad_mask & NURBS_GRAD_CTRL) && !grad_ctrl) || ((grad_mask & NURBS_GRAD_W) && !grad_w) ||
+        ((grad_mask & NURBS_GRAD_KU) && !grad_ku) || ((grad_mask & NURBS_GRAD_KV) && !grad_kv))
+        return fail(ctx, NURBS_EINVAL, "NULL gradient output for a requested gradient");
+    if (!ctrl || !w || !ku || !kv || !us || !vs) return fail(ctx, NURBS_EINVAL, "NULL array");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (nu_s == 0 || nv_s == 0) {
+        // no samples: every gradient is zero
+        const size_t cp = (size_t)B * nu_c * nv_c;
+        hipError_t e = hipSuccess;
+        if (grad_mask & NURBS_GRAD_CTRL) e = hipMemsetAsync(grad_ctrl, 0, cp * 3 * 4, st);
+        if (!e && (grad_mask & NURBS_GRAD_W)) e = hipMemsetAsync(grad_w, 0, cp * 4, st);
+        if (!e && (grad_mask & NURBS_GRAD_KU)) e = hipMemsetAsync(grad_ku, 0, (size_t)B * (nu_c + p + 1) * 4, st);
+        if (!e && (grad_mask & NURBS_GRAD_KV)) e = hipMemsetAsync(grad_kv, 0, (size_t)B * (nv_c + q + 1) * 4, st);
+        return e ? hip_fail(ctx, e, "hipMemsetAsync") : NURBS_OK;
+    }
+    if (!grad_pts) return fail(ctx, NURBS_EINVAL, "NULL grad_pts");
+    const UniformGeom g = uniform_geom(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
+    const size_t need = kWsHeader + (size_t)g.tiles_b * g.slot;
+    if (!ws || ws_bytes < need) return fail(ctx, NURBS_EWORKSPACE, "workspace too small: need " + std::to_string(need));
+    if (g.tiles_b > (1ll << 30)) return fail(ctx, NURBS_EINVAL, "batch too large");
+    UniformArgs a = make_uargs(ctx, g, true, B, nu_c, nv_c, nu_s, nv_s, ctrl, w, ku, kv, us, vs, uv_shared, ws);
+    char* slots = reinterpret_cast<char*>(ws) + kWsHeader;
+    const dim3 grid((unsigned)((g.tiles_b + kWavesPerWG - 1) / kWavesPerWG));
+    hipError_t e = hipErrorInvalidValue;
+    switch (p) {
+#define ND_CASE(P)                                                                                        \
+    case P:                                                                                               \
+        e = launch_uniform_bwd_p##P(q, grid, st, a, grad_pts, slots, g.slot, grad_mask);                  \
+        if (e == hipSuccess)                                                                              \
+            e = launch_uniform_fin_p##P(q, dim3(B), st, a, slots, g.slot, grad_ctrl, grad_w, grad_ku,      \
+                                        grad_kv, grad_mask);                                              \
+        break;
+        ND_CASE(1) ND_CASE(2) ND_CASE(3) ND_CASE(4) ND_CASE(5) ND_CASE(6) ND_CASE(7)
+#undef ND_CASE
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "launch backward");
+    return NURBS_OK;
+}
+
+// --------------------------------------------------------------------------
+// plans
+// --------------------------------------------------------------------------
+namespace {
+
+// relative cost of a tile (per-point work grows with the degree in u)
+double tile_cost(const nurbs_desc& d, int rows, bool bwd) {
+    const double cols = std::min(kWave, d.nv_s);
+    const double pts = rows * cols;
+    const double per_pt = bwd ? (12.0 * (d.p + 1) + 16.0) : (4.0 * (d.p + 1) + 12.0);
+    const double setup = bwd ? (double)(d.nu_c) * 40.0 * (d.q + 1) : 8.0 * (d.p + 1) * (d.q + 1);
+    return pts * per_pt + setup;
+}
+
+}  // namespace
+
+int nurbs_plan_create(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nurbs_plan** out,
+                      size_t* ws_bytes) {
+    if (!ctx) return fail(nullptr, NURBS_EINVAL, "ctx is NULL");
+    if (!out || (!host && n > 0) || n < 0) return fail(ctx, NURBS_EINVAL, "bad arguments");
+    if (flags & ~NURBS_VALIDATE) return fail(ctx, NURBS_EINVAL, "unknown flag bits");
+    *out = nullptr;
+    for (int s = 0; s < n; ++s) {
+        const nurbs_desc& d = host[s];
+        int rc = check_shape(ctx, d.p, d.q, d.nu_c, d.nv_c, d.nu_s, d.nv_s);
+        if (rc) {
+            ctx->err = "surface " + std::to_string(s) + ": " + ctx->err;
+            return rc;
+        }
+        if (d.ctrl_off < 0 || d.w_off < 0 || d.ku_off < 0 || d.kv_off < 0 || d.us_off < 0 || d.vs_off < 0 ||
+            d.pts_off < 0)
+            return fail(ctx, NURBS_EINVAL, "surface " + std::to_string(s) + ": negative offset");
+    }
+    nurbs_plan* pl = new nurbs_plan();
+    pl->ctx = ctx;
+    pl->device = ctx->device;
+    pl->n = n;
+    pl->flags = flags;
+    pl->host.assign(host, host + n);
+
+    // tiles
+    std::vector<DevDesc> dd(n);
+    std::vector<DevTile> ft, bt;
+    std::vector<double> fcost, bcost;
+    size_t slot_off = 0;
+    const int cus = std::max(ctx->num_cus, 1);
+    for (int s = 0; s < n; ++s) {
+        const nurbs_desc& d = pl->host[s];
+        DevDesc& x = dd[s];
+        x.p = d.p; x.q = d.q; x.nu_c = d.nu_c; x.nv_c = d.nv_c; x.nu_s = d.nu_s; x.nv_s = d.nv_s;
+        x.ctrl_off = d.ctrl_off; x.w_off = d.w_off; x.ku_off = d.ku_off; x.kv_off = d.kv_off;
+        x.us_off = d.us_off; x.vs_off = d.vs_off; x.pts_off = d.pts_off;
+        x.pad = 0;
+        const int ncb = (d.nv_s + kWave - 1) / kWave;
+        const int rf = tile_rows(d.nu_s, d.nv_s, kFwdTilePts);
+        const int rb = tile_rows(d.nu_s, d.nv_s, kBwdTilePts);
+        x.rows = rb;
+        x.tile_first = (int)bt.size();
+        int cnt = 0;
+        if (d.nu_s > 0 && d.nv_s > 0) {
+            for (int r0 = 0; r0 < d.nu_s; r0 += rf)
+                for (int cb = 0; cb < ncb; ++cb) {
+                    DevTile t{s, cb * kWave, r0, std::min(d.nu_s, r0 + rf), 0};
+                    ft.push_back(t);
+                    fcost.push_back(tile_cost(d, t.row1 - t.row0, false));
+                }
+            for (int r0 = 0; r0 < d.nu_s; r0 += rb)
+                for (int cb = 0; cb < ncb; ++cb) {
+                    DevTile t{s, cb * kWave, r0, std::min(d.nu_s, r0 + rb), (long long)(kWsHeader + slot_off)};
+                    slot_off += align16(slot_bytes(d.p, d.q, d.nu_c, d.nv_c, rb));
+                    bt.push_back(t);
+                    bcost.push_back(tile_cost(d, t.row1 - t.row0, true));
+                    ++cnt;
+                }
+        }
+        x.tile_count = cnt;
+        pl->max_nU = std::max(pl->max_nU, d.nu_c + d.p + 1);
+        pl->max_nV = std::max(pl->max_nV, d.nv_c + d.q + 1);
+    }
+    // execution order: most expensive first (greedy longest-processing-time)
+    std::vector<int> fo(ft.size()), bo(bt.size());
+    std::iota(fo.begin(), fo.end(), 0);
+    std::iota(bo.begin(), bo.end(), 0);
+    std::stable_sort(fo.begin(), fo.end(), [&](int a, int b) { return fcost[a] > fcost[b]; });
+    std::stable_sort(bo.begin(), bo.end(), [&](int a, int b) { return bcost[a] > bcost[b]; });
+    pl->nf = (int)ft.size();
+    pl->nb = (int)bt.size();
+    pl->ws_bytes = kWsHeader + slot_off;
+
+    // degree class and persistent grid: as many workgroups as fit at once
+    int maxdeg = 1;
+    for (const auto& d : pl->host) maxdeg = std::max(maxdeg, std::max(d.p, d.q));
+    pl->maxd = maxdeg <= 5 ? 5 : 7;
+    int occ_f = 0, occ_b = 0;
+    hipError_t e = pl->maxd == 5 ? occupancy_plan_fwd_d5(&occ_f) : occupancy_plan_fwd_d7(&occ_f);
+    if (e == hipSuccess) e = pl->maxd == 5 ? occupancy_plan_bwd_d5(&occ_b) : occupancy_plan_bwd_d7(&occ_b);
+    if (e != hipSuccess) {
+        delete pl;
+        return hip_fail(ctx, e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    }
+    pl->grid_fwd = std::max(1, std::min(occ_f * cus, (pl->nf + kWavesPerWG - 1) / kWavesPerWG));
+    pl->grid_bwd = std::max(1, std::min(occ_b * cus, (pl->nb + kWavesPerWG - 1) / kWavesPerWG));
+
+    // upload tables
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t o_desc = 0;
+    const size_t o_ft = o_desc + al(sizeof(DevDesc) * std::max(n, 1));
+    const size_t o_fo = o_ft + al(sizeof(DevTile) * std::max<size_t>(ft.size(), 1));
+    const size_t o_bt = o_fo + al(sizeof(int) * std::max<size_t>(fo.size(), 1));
+    const size_t o_bo = o_bt + al(sizeof(DevTile) * std::max<size_t>(bt.size(), 1));
+    const size_t o_ct = o_bo + al(sizeof(int) * std::max<size_t>(bo.size(), 1));
+    const size_t total = o_ct + 256;
+    std::vector<char> blob(total, 0);
+    if (n) memcpy(blob.data() + o_desc, dd.data(), sizeof(DevDesc) * n);
+    if (!ft.empty()) memcpy(blob.data() + o_ft, ft.data(), sizeof(DevTile) * ft.size());
+    if (!fo.empty()) memcpy(blob.data() + o_fo, fo.data(), sizeof(int) * fo.size());
+    if (!bt.empty()) memcpy(blob.data() + o_bt, bt.data(), sizeof(DevTile) * bt.size());
+    if (!bo.empty()) memcpy(blob.data() + o_bo, bo.data(), sizeof(int) * bo.size());
+    e = hipMalloc(&pl->dev, total);
+    if (e != hipSuccess) {
+        delete pl;
+        return hip_fail(ctx, e, "hipMalloc(plan tables)");
+    }
+    e = hipMemcpy(pl->dev, blob.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(pl->dev);
+        delete pl;
+        return hip_fail(ctx, e, "hipMemcpy(plan tables)");
+    }
+    char* base = reinterpret_cast<char*>(pl->dev);
+    pl->d_desc = reinterpret_cast<DevDesc*>(base + o_desc);
+    pl->d_ftiles = reinterpret_cast<DevTile*>(base + o_ft);
+    pl->d_forder = reinterpret_cast<int*>(base + o_fo);
+    pl->d_btiles = reinterpret_cast<DevTile*>(base + o_bt);
+    pl->d_border = reinterpret_cast<int*>(base + o_bo);
+    pl->d_counters = reinterpret_cast<unsigned*>(base + o_ct);
+    *out = pl;
+    if (ws_bytes) *ws_bytes = pl->ws_bytes;
+    return NURBS_OK;
+}
+
+int nurbs_plan_destroy(nurbs_plan* plan) {
+    if (!plan) return NURBS_OK;
+    if (plan->dev) (void)hipFree(plan->dev);
+    delete plan;
+    return NURBS_OK;
+}
+
+int nurbs_plan_info(nurbs_plan* plan, int* fwd_tiles, int* bwd_tiles, int* grid) {
+    if (!plan) return fail(nullptr, NURBS_EINVAL, "plan is NULL");
+    if (fwd_tiles) *fwd_tiles = plan->nf;
+    if (bwd_tiles) *bwd_tiles = plan->nb;
+    if (grid) *grid = plan->grid_bwd;
+    return NURBS_OK;
+}
+
+namespace {
+PlanArgs plan_args(nurbs_plan* pl, bool bwd, void* ws, const float* ctrl, const float* w, const float* ku,
+                   const float* kv, const float* us, const float* vs) {
+    PlanArgs a;
+    a.desc = pl->d_desc;
+    a.tiles = bwd ? pl->d_btiles : pl->d_ftiles;
+    a.order = bwd ? pl->d_border : pl->d_forder;
+    a.ntiles = bwd ? pl->nb : pl->nf;
+    a.counter = pl->d_counters + (bwd ? 2 : 0);
+    a.nwaves = (bwd ? pl->grid_bwd : pl->grid_fwd) * kWavesPerWG;
+    a.flags = pl->flags;
+    a.err = (pl->flags & NURBS_VALIDATE) ? reinterpret_cast<int*>(ws) : nullptr;
+    a.ctrl = ctrl; a.w = w; a.ku = ku; a.kv = kv; a.us = us; a.vs = vs;
+    return a;
+}
+}  // namespace
+
+int nurbs_plan_fwd(nurbs_plan* pl, const float* ctrl, const float* w, const float* ku, const float* kv,
+                   const float* us, const float* vs, float* pts, void* ws, size_t ws_bytes, void* stream) {
+    if (!pl) return fail(nullptr, NURBS_EINVAL, "plan is NULL");
+    if (pl->nf == 0) return NURBS_OK;
+    if (!ctrl || !w || !ku || !kv || !us || !vs || !pts) return fail(pl->ctx, NURBS_EINVAL, "NULL array");
+    if ((pl->flags & NURBS_VALIDATE) && (!ws || ws_bytes < kWsHeader))
+        return fail(pl->ctx, NURBS_EWORKSPACE, "NURBS_VALIDATE needs a workspace");
+    PlanArgs a = plan_args(pl, false, ws, ctrl, w, ku, kv, us, vs);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = pl->maxd == 5 ? launch_plan_fwd_d5(dim3(pl->grid_fwd), st, a, pts)
+                                 : launch_plan_fwd_d7(dim3(pl->grid_fwd), st, a, pts);
+    if (e != hipSuccess) return hip_fail(pl->ctx, e, "launch plan forward");
+    return NURBS_OK;
+}
+
+int nurbs_plan_bwd(nurbs_plan* pl, const float* ctrl, const float* w, const float* ku, const float* kv,
+                   const float* us, const float* vs, const float* grad_pts, float* grad_ctrl, float* grad_w,
+                   float* grad_ku, float* grad_kv, unsigned grad_mask, void* ws, size_t ws_bytes, void* stream) {
+    if (!pl) return fail(nullptr, NURBS_EINVAL, "plan is NULL");
+    if (grad_mask & ~NURBS_GRAD_ALL) return fail(pl->ctx, NURBS_EINVAL, "unknown gradient bits");
+    if (grad_mask == 0 || pl->n == 0) return NURBS_OK;
+    if (((grad_mask & NURBS_GRAD_CTRL) && !grad_ctrl) || ((grad_mask & NURBS_GRAD_W) && !grad_w) ||
+        ((grad_mask & NURBS_GRAD_KU) && !grad_ku) || ((grad_mask & NURBS_GRAD_KV) && !grad_kv))
+        return fail(pl->ctx, NURBS_EINVAL, "NULL gradient output for a requested gradient");
+    if (!ctrl || !w || !ku || !kv || !us || !vs || !grad_pts) return fail(pl->ctx, NURBS_EINVAL, "NULL array");
+    if (!ws || ws_bytes < pl->ws_bytes)
+        return fail(pl->ctx, NURBS_EWORKSPACE, "workspace too small: need " + std::to_string(pl->ws_bytes));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    PlanArgs a = plan_args(pl, true, ws, ctrl, w, ku, kv, us, vs);
+    char* slots = reinterpret_cast<char*>(ws);
+    hipError_t e = hipSuccess;
+    if (pl->nb > 0)
+        e = pl->maxd == 5 ? launch_plan_bwd_d5(dim3(pl->grid_bwd), st, a, grad_pts, slots, grad_mask)
+                          : launch_plan_bwd_d7(dim3(pl->grid_bwd), st, a, grad_pts, slots, grad_mask);
+    if (e == hipSuccess)
+        e = pl->maxd == 5
+                ? launch_plan_fin_d5(dim3(pl->n), st, a, slots, grad_ctrl, grad_w, grad_ku, grad_kv, grad_mask)
+                : launch_plan_fin_d7(dim3(pl->n), st, a, slots, grad_ctrl, grad_w, grad_ku, grad_kv, grad_mask);
+    if (e != hipSuccess) return hip_fail(pl->ctx, e, "launch plan backward");
+    return NURBS_OK;
+}
+
+// --------------------------------------------------------------------------
+// test exports and device errors
+// --------------------------------------------------------------------------
+int nurbs_find_spans(const float* knots, int n_knots, int p, const float* x, int nx, int32_t* spans, void* stream) {
+    if (p < 1 || p > NURBS_MAX_DEGREE) return fail(nullptr, NURBS_EDEGREE, "degree");
+    if (n_knots < 2 * p + 2 || nx < 0 || !knots || (nx > 0 && (!x || !spans)))
+        return fail(nullptr, NURBS_EINVAL, "bad arguments");
+    if (nx == 0) return NURBS_OK;
+    hipError_t e = launch_spans(p, reinterpret_cast<hipStream_t>(stream), knots, n_knots, x, nx, spans, nullptr);
+    return e ? hip_fail(nullptr, e, "launch k_spans") : NURBS_OK;
+}
+
+int nurbs_basis(const float* knots, int n_knots, int p, const float* x, int nx, float* N, void* stream) {
+    if (p < 1 || p > NURBS_MAX_DEGREE) return fail(nullptr, NURBS_EDEGREE, "degree");
+    if (n_knots < 2 * p + 2 || nx < 0 || !knots || (nx > 0 && (!x || !N)))
+        return fail(nullptr, NURBS_EINVAL, "bad arguments");
+    if (nx == 0) return NURBS_OK;
+    hipError_t e = launch_spans(p, reinterpret_cast<hipStream_t>(stream), knots, n_knots, x, nx, nullptr, N);
+    return e ? hip_fail(nullptr, e, "launch k_spans") : NURBS_OK;
+}
+
+int nurbs_read_device_error(const void* ws, void* stream, int* code) {
+    if (!ws || !code) return fail(nullptr, NURBS_EINVAL, "bad arguments");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int v = 0;
+    hipError_t e = hipMemcpyAsync(&v, ws, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemsetAsync(const_cast<void*>(ws), 0, sizeof(int), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "read device error");
+    *code = v;
+    return NURBS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,250 @@
+// Device building blocks for NURBS surface evaluation on gfx950 (wave64).
+//
+// Span search and basis (Sec. 3.1.2 steps 1-2 of NURBS-Diff, eqs. NURBSBasis
+// and BSplineBasis2), the homogeneous control point (Sec. 3.1.2 step 3), the
+// reverse-mode knot derivative of the recursion (Sec. 3.2.1) and wave-level
+// helpers.  Per-row / per-column set-up work (span, basis, knot derivatives)
+// runs in FP64: it is O(nu_s + nv_s) per surface, so its cost is not
+// measurable next to the O(nu_s * nv_s) per-point work, which runs in FP32.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nd {
+
+constexpr int kWave = 64;
+constexpr int kWavesPerWG = 4;
+constexpr int kWG = kWave * kWavesPerWG;
+constexpr int kMaxDeg = 7;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ int bcast_lane(int x, int l) {
+    return __builtin_amdgcn_readlane(x, l);
+}
+__device__ __forceinline__ float bcast_lane(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ long long uniform64(long long x) {
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(x & 0xffffffffll));
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)x >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Order this wave's LDS traffic: everything before is visible to every lane
+// after (LDS executes in order per wave; this stops compiler reordering).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 1/x from the hardware reciprocal plus one Newton-Raphson step
+// (r <- r + r(1 - x r)), about 0.5 ulp for the normal range used here.
+__device__ __forceinline__ float recip(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    float e = __builtin_fmaf(-x, r, 1.0f);
+    return __builtin_fmaf(r, e, r);
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) x += __shfl_xor(x, m, kWave);
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// knot span and basis
+// ---------------------------------------------------------------------------
+
+// Clamp a parameter into the domain [U_deg, U_{n+1}] (n+1 = control points).
+__device__ __forceinline__ float clamp_param(const float* __restrict__ U, int deg, int n, float x) {
+    return fminf(fmaxf(x, U[deg]), U[n + 1]);
+}
+
+// Half-open span: the k in [deg, n] with U_k <= x < U_{k+1}; x == U_{n+1}
+// gives n.  Binary search over float comparisons, so the result is exact.
+__device__ __forceinline__ int find_span(const float* __restrict__ U, int deg, int n, float x) {
+    if (x >= U[n + 1]) return n;
+    int lo = deg, hi = n + 1;  // invariant: U[lo] <= x < U[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (U[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// The D+1 non-zero basis functions N_{k-D..k}^D(x) on span k, by the
+// triangular Cox-de Boor scheme with left/right knot distances.  Every
+// denominator is a knot difference that contains [U_k, U_{k+1}], so it is
+// positive on a non-empty span.
+template <int D>
+__device__ __forceinline__ void basis_f64(const float* __restrict__ U, int k, float xf, double N[D + 1]) {
+    const double x = xf;
+    double left[D + 1], right[D + 1];
+    N[0] = 1.0;
+#pragma unroll
+    for (int j = 1; j <= D; ++j) {
+        left[j] = x - (double)U[k + 1 - j];
+        right[j] = (double)U[k + j] - x;
+        double saved = 0.0;
+#pragma unroll
+        for (int r = 0; r < j; ++r) {
+            const double tmp = N[r] / (right[r + 1] + left[j - r]);
+            N[r] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        N[j] = saved;
+    }
+}
+
+// Reverse-mode derivative of Phi = sum_r e[r] N_{k-D+r}^D(x) with respect to
+// the knots U_{k-D} .. U_{k+D+1} (gU[t] <-> U_{k-D+t}), through the
+// recursion N_i^d = alpha N_i^{d-1} + beta N_{i+1}^{d-1},
+// alpha = (x-U_i)/(U_{i+d}-U_i), beta = (U_{i+d+1}-x)/(U_{i+d+1}-U_{i+1}).
+// The degree-0 indicator contributes no knot derivative (zero-bandwidth
+// limit of the paper's smoothing), so only the alpha/beta factors do.
+template <int D>
+__device__ __forceinline__ void basis_knot_adjoint(const float* __restrict__ U, int k, float xf,
+                                                   const double e[D + 1], double gU[2 * D + 2]) {
+    const double x = xf;
+    // forward triangle T[d][idx] = N_{k-d+idx}^d
+    double T[D + 1][D + 1];
+    T[0][0] = 1.0;
+#pragma unroll
+    for (int d = 1; d <= D; ++d) {
+#pragma unroll
+        for (int idx = 0; idx <= d; ++idx) {
+            const int i = k - d + idx;
+            double v = 0.0;
+            if (idx >= 1) {
+                const double den = (double)U[i + d] - (double)U[i];
+                if (den != 0.0) v += (x - (double)U[i]) / den * T[d - 1][idx - 1];
+            }
+            if (idx <= d - 1) {
+                const double den = (double)U[i + d + 1] - (double)U[i + 1];
+                if (den != 0.0) v += ((double)U[i + d + 1] - x) / den * T[d - 1][idx];
+            }
+            T[d][idx] = v;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 2 * D + 2; ++t) gU[t] = 0.0;
+    double A[D + 1];
+#pragma unroll
+    for (int r = 0; r <= D; ++r) A[r] = e[r];
+#pragma unroll
+    for (int d = D; d >= 1; --d) {
+        double An[D + 1];
+#pragma unroll
+        for (int r = 0; r <= D; ++r) An[r] = 0.0;
+#pragma unroll
+        for (int idx = 0; idx <= d; ++idx) {
+            const int i = k - d + idx;
+            const int t = D - d + idx;  // window slot of U_i
+            const double Ai = A[idx];
+            if (idx >= 1) {
+                const double Ui = U[i], Uid = U[i + d];
+                const double den = Uid - Ui;
+                if (den != 0.0) {
+                    const double Np = T[d - 1][idx - 1];
+                    const double inv2 = 1.0 / (den * den);
+                    An[idx - 1] += Ai * (x - Ui) / den;
+                    gU[t] += Ai * Np * (x - Uid) * inv2;
+                    gU[t + d] -= Ai * Np * (x - Ui) * inv2;
+                }
+            }
+            if (idx <= d - 1) {
+                const double Ui1 = U[i + 1], Uid1 = U[i + d + 1];
+                const double den = Uid1 - Ui1;
+                if (den != 0.0) {
+                    const double Np = T[d - 1][idx];
+                    const double inv2 = 1.0 / (den * den);
+                    An[idx] += Ai * (Uid1 - x) / den;
+                    gU[t + 1] += Ai * Np * (Uid1 - x) * inv2;
+                    gU[t + d + 1] += Ai * Np * (x - Ui1) * inv2;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r <= D; ++r) A[r] = An[r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// one surface's arrays
+// ---------------------------------------------------------------------------
+struct Surf {
+    const float* __restrict__ ctrl;  // [nu_c][nv_c][3]
+    const float* __restrict__ w;     // [nu_c][nv_c]
+    const float* __restrict__ ku;    // [nu_c+p+1]
+    const float* __restrict__ kv;    // [nv_c+q+1]
+    const float* __restrict__ us;    // [nu_s]
+    const float* __restrict__ vs;    // [nv_s]
+    int nu_c, nv_c, nu_s, nv_s;
+};
+
+// homogeneous control point Pw_ij = (w x, w y, w z, w)
+__device__ __forceinline__ float4 load_pw(const Surf& s, int i, int j) {
+    const int ij = i * s.nv_c + j;
+    const float* c = s.ctrl + 3 * ij;
+    const float wt = s.w[ij];
+    return make_float4(c[0] * wt, c[1] * wt, c[2] * wt, wt);
+}
+
+__device__ __forceinline__ float4 fma4(float a, float4 x, float4 y) {
+    return make_float4(__builtin_fmaf(a, x.x, y.x), __builtin_fmaf(a, x.y, y.y),
+                       __builtin_fmaf(a, x.z, y.z), __builtin_fmaf(a, x.w, y.w));
+}
+__device__ __forceinline__ float dot4(float4 a, float4 b) {
+    return __builtin_fmaf(a.x, b.x, __builtin_fmaf(a.y, b.y, __builtin_fmaf(a.z, b.z, a.w * b.w)));
+}
+
+// R_i(b) = sum_h Nv_h(v_b) Pw[i][jb + h]: control row i contracted along v
+// for this lane's sample column (jb = span_v - q).  q <= QM is uniform.
+template <int QM>
+__device__ __forceinline__ float4 row_contract(const Surf& s, int i, int jb, const float Nv[QM + 1], int q) {
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int h = 0; h <= QM; ++h)
+        if (h <= q) acc = fma4(Nv[h], load_pw(s, i, jb + h), acc);
+    return acc;
+}
+
+// Span and FP32 basis of one sample along a direction with degree D.
+template <int D>
+__device__ __forceinline__ int sample_basis(const float* __restrict__ U, int nc, float x, float N[D + 1]) {
+    const int n = nc - 1;
+    const float xc = clamp_param(U, D, n, x);
+    const int k = find_span(U, D, n, xc);
+    double Nd[D + 1];
+    basis_f64<D>(U, k, xc, Nd);
+#pragma unroll
+    for (int r = 0; r <= D; ++r) N[r] = (float)Nd[r];
+    return k;
+}
+
+// The same with a uniform runtime degree d <= DM; N[d+1..DM] are set to 0.
+template <int DM>
+__device__ __forceinline__ int sample_basis_rt(const float* __restrict__ U, int nc, float x, int d, float N[DM + 1]) {
+#pragma unroll
+    for (int r = 0; r <= DM; ++r) N[r] = 0.f;
+    int k = 0;
+    switch (d) {
+#define ND_SB(D)                                                      \
+    case D:                                                           \
+        if constexpr (D <= DM) {                                      \
+            float t[D + 1];                                           \
+            k = sample_basis<D>(U, nc, x, t);                         \
+            _Pragma("unroll") for (int r = 0; r <= D; ++r) N[r] = t[r]; \
+        }                                                             \
+        break;
+        ND_SB(1) ND_SB(2) ND_SB(3) ND_SB(4) ND_SB(5) ND_SB(6) ND_SB(7)
+#undef ND_SB
+        default: break;
+    }
+    return k;
+}
+
+}  // namespace nd

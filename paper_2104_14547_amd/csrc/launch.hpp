@@ -1,0 +1,81 @@
+// Kernel argument blocks and launcher entry points shared by the kernel
+// translation units and the host ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace nd {
+
+// B surfaces of one shape; tile index arithmetic, no tables.
+struct UniformArgs {
+    const float *ctrl, *w, *ku, *kv, *us, *vs;
+    int B, nu_c, nv_c, nu_s, nv_s, uv_shared;
+    int ncb, nrb, rows;  // column blocks, row blocks, rows per tile
+    int ntiles;
+    unsigned flags;
+    int* err;
+};
+
+// One surface of a ragged batch, as the device sees it.
+struct DevDesc {
+    int p, q, nu_c, nv_c, nu_s, nv_s;
+    long long ctrl_off, w_off, ku_off, kv_off, us_off, vs_off, pts_off;
+    int tile_first, tile_count;  // backward tiles of this surface, natural order
+    int rows;                    // rows per backward tile of this surface
+    int pad;
+};
+
+// One tile of a ragged batch.
+struct DevTile {
+    int surf, col0, row0, row1;
+    long long slot_off;  // backward: byte offset of the tile's workspace slot
+};
+
+struct PlanArgs {
+    const DevDesc* desc;
+    const DevTile* tiles;  // natural order
+    const int* order;      // execution order (indices into tiles)
+    int ntiles;
+    unsigned* counter;     // [0] = next tile, [1] = finished waves
+    int nwaves;            // persistent waves in the grid
+    unsigned flags;
+    int* err;
+    const float *ctrl, *w, *ku, *kv, *us, *vs;
+};
+
+// uniform batch, one entry per degree in u (defined in k_uniform_p<P>.hip)
+#define ND_DECLARE_UNIFORM(P)                                                                          \
+    hipError_t launch_uniform_fwd_p##P(int q, dim3 grid, hipStream_t st, const UniformArgs& a,         \
+                                       float* pts);                                                    \
+    hipError_t launch_uniform_bwd_p##P(int q, dim3 grid, hipStream_t st, const UniformArgs& a,         \
+                                       const float* gpts, char* slots, size_t slot_sz, unsigned mask); \
+    hipError_t launch_uniform_fin_p##P(int q, dim3 grid, hipStream_t st, const UniformArgs& a,         \
+                                       const char* slots, size_t slot_sz, float* gc, float* gw,        \
+                                       float* gku, float* gkv, unsigned mask);
+ND_DECLARE_UNIFORM(1)
+ND_DECLARE_UNIFORM(2)
+ND_DECLARE_UNIFORM(3)
+ND_DECLARE_UNIFORM(4)
+ND_DECLARE_UNIFORM(5)
+ND_DECLARE_UNIFORM(6)
+ND_DECLARE_UNIFORM(7)
+#undef ND_DECLARE_UNIFORM
+
+// ragged batch: persistent kernels for degree class <= 5 and <= 7
+#define ND_DECLARE_PLAN(M)                                                                            \
+    hipError_t launch_plan_fwd_d##M(dim3 grid, hipStream_t st, const PlanArgs& a, float* pts);        \
+    hipError_t launch_plan_bwd_d##M(dim3 grid, hipStream_t st, const PlanArgs& a, const float* gpts,  \
+                                    char* slots, unsigned mask);                                      \
+    hipError_t launch_plan_fin_d##M(dim3 grid, hipStream_t st, const PlanArgs& a, const char* slots,  \
+                                    float* gc, float* gw, float* gku, float* gkv, unsigned mask);     \
+    hipError_t occupancy_plan_fwd_d##M(int* blocks_per_cu);                                           \
+    hipError_t occupancy_plan_bwd_d##M(int* blocks_per_cu);
+ND_DECLARE_PLAN(5)
+ND_DECLARE_PLAN(7)
+#undef ND_DECLARE_PLAN
+
+// test exports
+hipError_t launch_spans(int p, hipStream_t st, const float* U, int nk, const float* x, int nx, int* spans,
+                        float* N);
+
+}  // namespace nd

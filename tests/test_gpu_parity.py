@@ -1,0 +1,395 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C ABI).
+
+Bars:
+  * knot spans: bit-exact;
+  * points: per surface, max_ab |S_gpu - S_oracle|_2 <= 1e-5 * diag(bbox(S_oracle));
+  * gradients: per surface and per tensor, |X_gpu - X_oracle|_inf <= 1e-4 * |X_oracle|_inf.
+Backward parity feeds both sides the same float32 upstream gradient dL/dS.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2104_14547_amd as nd  # noqa: E402
+from paper_2104_14547_amd import workloads as W  # noqa: E402
+from oracle import oracle as O  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+PTS_TOL = 1e-5
+GRAD_TOL = 1e-4
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev())
+
+
+def H(t):
+    return t.detach().cpu().numpy()
+
+
+def check_points(batch, got, want, tol=PTS_TOL):
+    worst = 0.0
+    for s in range(batch.n):
+        _, _, _, _, nu_s, nv_s = (int(x) for x in batch.shapes[s])
+        if nu_s * nv_s == 0:
+            continue
+        o = int(batch.offsets[s, 6])
+        g = np.asarray(got[o:o + nu_s * nv_s * 3], np.float64).reshape(-1, 3)
+        w = want[o:o + nu_s * nv_s * 3].reshape(-1, 3)
+        diag = np.linalg.norm(w.max(0) - w.min(0))
+        if diag == 0.0:  # a single sample: measure against the control net's extent
+            c = batch.surface(s)["ctrl"].reshape(-1, 3).astype(np.float64)
+            diag = np.linalg.norm(c.max(0) - c.min(0))
+        err = np.linalg.norm(g - w, axis=1).max() / max(diag, 1e-30)
+        worst = max(worst, err)
+        assert err <= tol, f"surface {s}: point error {err:.3e} of the bbox diagonal"
+    return worst
+
+
+def grad_slices(batch, s):
+    p, q, nu_c, nv_c, _, _ = (int(x) for x in batch.shapes[s])
+    o = batch.offsets[s]
+    return {"ctrl": slice(int(o[0]), int(o[0]) + nu_c * nv_c * 3),
+            "w": slice(int(o[1]), int(o[1]) + nu_c * nv_c),
+            "ku": slice(int(o[2]), int(o[2]) + nu_c + p + 1),
+            "kv": slice(int(o[3]), int(o[3]) + nv_c + q + 1)}
+
+
+def check_grads(batch, got, want, tol=GRAD_TOL, names=("ctrl", "w", "ku", "kv")):
+    worst = {}
+    for s in range(batch.n):
+        sl = grad_slices(batch, s)
+        for name, g, w in zip(("ctrl", "w", "ku", "kv"), got, want):
+            if name not in names:
+                continue
+            gs = np.asarray(g[sl[name]], np.float64)
+            ws = w[sl[name]]
+            scale = np.abs(ws).max()
+            err = np.abs(gs - ws).max() / scale if scale > 0 else np.abs(gs).max()
+            worst[name] = max(worst.get(name, 0.0), err)
+            assert err <= tol, f"surface {s} grad {name}: rel err {err:.3e}"
+    return worst
+
+
+def plan_run(batch, upstream, mask=nd.NURBS_GRAD_ALL, validate=False):
+    sb = nd.SurfaceBatch(batch.shapes, batch.offsets, device=0, validate=validate)
+    args = [T(getattr(batch, k)) for k in ("ctrl", "w", "ku", "kv", "us", "vs")]
+    pts = sb.forward(*args)
+    grads = sb.backward(*args, T(upstream), mask=mask)
+    torch.cuda.synchronize()
+    return sb, H(pts), [None if g is None else H(g) for g in grads]
+
+
+def oracle_both(batch, upstream, nthreads=0):
+    S = O.fwd(batch, local=True, nthreads=nthreads)
+    G = O.bwd(batch, upstream.astype(np.float64), local=True, nthreads=nthreads)
+    return S, G
+
+
+# --------------------------------------------------------------------------
+# span search and basis (test exports)
+# --------------------------------------------------------------------------
+
+def knot_cases():
+    g = np.random.Generator(np.random.PCG64(7))
+    cases = [(np.array([0, 0, 0, 0, .2, .4, .6, .8, 1, 1, 1, 1], np.float32), 3),
+             (np.array([0, 0, 0, .5, .5, 1, 1, 1], np.float32), 2),
+             (np.array([0, 0, .25, .25, .5, .75, 1, 1], np.float32), 1)]
+    for p in range(1, 8):
+        k = W.clamped_random_knots(g, p + 1 + int(g.integers(0, 30)), p, 0.3)
+        cases.append((k, p))
+    # clustered interior knots
+    k = np.concatenate([np.zeros(4), 0.5 + 1e-5 * np.arange(6), np.ones(4)]).astype(np.float32)
+    cases.append((k, 3))
+    return cases
+
+
+@pytest.mark.parametrize("case", range(len(knot_cases())))
+def test_spans_bit_exact_and_basis(case):
+    U, p = knot_cases()[case]
+    g = np.random.Generator(np.random.PCG64(100 + case))
+    x = np.concatenate([g.uniform(0, 1, 500), U, [0.0, 1.0, -0.5, 1.5],
+                        np.nextafter(U, np.float32(2)), np.nextafter(U, np.float32(-1))]).astype(np.float32)
+    spans = H(nd.find_spans(T(U), p, T(x)))
+    want = np.array([O.find_span(U.astype(np.float64), p, float(v)) for v in x])
+    assert np.array_equal(spans, want)
+    Nb = H(nd.basis(T(U), p, T(x)))
+    for i, v in enumerate(x):
+        k, Nl, _, _ = O.basis_local(U.astype(np.float64), p, float(v))
+        assert k == spans[i]
+        np.testing.assert_allclose(Nb[i], Nl, rtol=0, atol=1.2e-7)
+
+
+# --------------------------------------------------------------------------
+# uniform batches
+# --------------------------------------------------------------------------
+
+def uniform_run(batch, upstream, mask=nd.NURBS_GRAD_ALL):
+    s0 = batch.surface(0)
+    B = batch.n
+    p, q, nu_c, nv_c, nu_s, nv_s = (int(x) for x in batch.shapes[0])
+    ctrl = T(batch.ctrl.reshape(B, nu_c, nv_c, 3))
+    w = T(batch.w.reshape(B, nu_c, nv_c))
+    ku = T(batch.ku.reshape(B, -1))
+    kv = T(batch.kv.reshape(B, -1))
+    shared = all(np.array_equal(batch.surface(i)["us"], s0["us"]) and
+                 np.array_equal(batch.surface(i)["vs"], s0["vs"]) for i in range(B))
+    if shared:
+        us, vs = T(s0["us"]), T(s0["vs"])
+    else:
+        us, vs = T(batch.us.reshape(B, nu_s)), T(batch.vs.reshape(B, nv_s))
+    pts = nd.surface_fwd(ctrl, w, ku, kv, p, q, us, vs)
+    g = nd.surface_bwd(ctrl, w, ku, kv, p, q, us, vs, T(upstream.reshape(B, nu_s, nv_s, 3)), mask)
+    torch.cuda.synchronize()
+    return H(pts).ravel(), [None if x is None else H(x).ravel() for x in g]
+
+
+def loss_upstream(batch, S_or):
+    """dL/dS = 2 (S - T) for L = sum |S - T|^2, from the oracle's S, in float32."""
+    return (2.0 * (S_or - batch.target.astype(np.float64))).astype(np.float32)
+
+
+def test_single_bicubic_fwd_bwd():
+    b = W.single_bicubic(0)
+    S_or = O.fwd(b)  # dense: the definition
+    up = loss_upstream(b, S_or)
+    G_or = O.bwd(b, up.astype(np.float64))
+    pts, grads = uniform_run(b, up)
+    check_points(b, pts, S_or)
+    check_grads(b, grads, G_or)
+
+
+def test_batch_bicubic_full_size():
+    b = W.batch_bicubic(1)
+    S_or = O.fwd(b, local=True)
+    up = loss_upstream(b, S_or)
+    G_or = O.bwd(b, up.astype(np.float64), local=True)
+    pts, grads = uniform_run(b, up)
+    check_points(b, pts, S_or)
+    check_grads(b, grads, G_or)
+
+
+def one_surface(seed, p, q, nu_c, nv_c, nu_s, nv_s, repeat=0.0, on_knots=False, clustered=False):
+    g = np.random.Generator(np.random.PCG64(seed))
+    d = dict(p=p, q=q, nu_c=nu_c, nv_c=nv_c, nu_s=nu_s, nv_s=nv_s)
+    d["ctrl"] = W.perturbed_lattice(g, nu_c, nv_c)
+    d["w"] = g.uniform(0.5, 1.5, (nu_c, nv_c)).astype(np.float32)
+    d["ku"] = W.clamped_random_knots(g, nu_c, p, repeat)
+    d["kv"] = W.clamped_random_knots(g, nv_c, q, repeat)
+    if clustered:
+        n_int = nu_c - p - 1
+        d["ku"][p + 1:p + 1 + n_int] = (0.4 + 2e-5 * np.arange(n_int)).astype(np.float32)
+    d["us"] = W.uniform_grid(nu_s)
+    d["vs"] = W.uniform_grid(nv_s)
+    if on_knots:
+        ku_in = np.unique(d["ku"])
+        d["us"] = np.sort(np.concatenate([d["us"][:max(nu_s - len(ku_in), 0)], ku_in]))[:nu_s].astype(np.float32)
+        kv_in = np.unique(d["kv"])
+        d["vs"] = np.sort(np.concatenate([d["vs"][:max(nv_s - len(kv_in), 0)], kv_in]))[:nv_s].astype(np.float32)
+    d["upstream"] = g.uniform(-0.1, 0.1, (nu_s, nv_s, 3)).astype(np.float32)
+    return d
+
+
+EDGE = [
+    # (p, q, nu_c, nv_c, nu_s, nv_s, repeat, on_knots, clustered)
+    (1, 1, 2, 2, 1, 1, 0.0, False, False),
+    (1, 2, 3, 5, 7, 3, 0.0, False, False),
+    (3, 3, 4, 4, 64, 64, 0.0, False, False),      # Bezier patch, exactly one column block
+    (2, 3, 30, 40, 10, 13, 0.0, False, False),    # samples sparser than spans
+    (5, 5, 6, 9, 130, 200, 0.3, False, False),    # ragged row tiles and column blocks
+    (7, 7, 8, 9, 65, 129, 0.0, False, False),     # degree-7 class
+    (3, 2, 9, 9, 257, 65, 0.3, True, False),      # samples on knots, repeated knots
+    (4, 1, 12, 3, 33, 300, 0.4, True, False),
+    (3, 3, 12, 12, 40, 40, 0.0, False, True),     # clustered knots
+    (6, 2, 40, 48, 20, 250, 0.2, False, False),
+]
+
+
+@pytest.mark.parametrize("i", range(len(EDGE)))
+def test_edge_cases_uniform_and_plan(i):
+    p, q, nu_c, nv_c, nu_s, nv_s, rep, on_knots, clustered = EDGE[i]
+    parts = [one_surface(1000 * i + j, p, q, nu_c, nv_c, nu_s, nv_s, rep, on_knots, clustered) for j in range(2)]
+    for j in range(2):  # uniform API needs one knot vector per surface but shared samples
+        parts[j]["us"], parts[j]["vs"] = parts[0]["us"], parts[0]["vs"]
+    b = W.pack("edge", parts)
+    S_or, G_or = oracle_both(b, b.upstream)
+    pts, grads = uniform_run(b, b.upstream)
+    check_points(b, pts, S_or)
+    check_grads(b, grads, G_or)
+    _, ppts, pgrads = plan_run(b, b.upstream)
+    assert np.array_equal(ppts, pts), "plan and uniform forward differ"
+    for x, y in zip(pgrads, grads):
+        assert np.array_equal(x, y), "plan and uniform backward differ"
+
+
+# --------------------------------------------------------------------------
+# ragged batches (plan)
+# --------------------------------------------------------------------------
+
+def uneven_subset():
+    full = W.uneven_batch(3, n_surf=4096)
+    sh = full.shapes
+    g = np.random.Generator(np.random.PCG64(5))
+    pick = set(g.choice(full.n, 48, replace=False).tolist())
+    pick |= set(np.nonzero((sh[:, 0] == 5) & (sh[:, 1] == 5))[0][:12].tolist())
+    big = np.argsort(-(sh[:, 4].astype(np.int64) * sh[:, 5]))[:4]
+    pick |= set(big.tolist())
+    for s in range(full.n):  # repeated interior knots
+        d = full.surface(s)
+        inner = d["ku"][d["p"] + 1:d["nu_c"]]
+        if len(inner) > 1 and (np.diff(inner) == 0).any():
+            pick.add(s)
+        if len(pick) >= 80:
+            break
+    return full.subset(sorted(pick))
+
+
+def test_uneven_subset_plan():
+    b = uneven_subset()
+    S_or, G_or = oracle_both(b, b.upstream)
+    sb, pts, grads = plan_run(b, b.upstream)
+    check_points(b, pts, S_or)
+    check_grads(b, grads, G_or)
+
+
+def test_plan_is_deterministic_and_batch_invariant():
+    b = uneven_subset()
+    _, pts1, g1 = plan_run(b, b.upstream)
+    _, pts2, g2 = plan_run(b, b.upstream)
+    assert np.array_equal(pts1, pts2)
+    for x, y in zip(g1, g2):
+        assert np.array_equal(x, y)
+    # each surface alone gives bitwise the same result as inside the mix
+    for s in (0, 7, b.n - 1):
+        one = b.subset([s])
+        _, p1, gg = plan_run(one, one.upstream)
+        o = b.offsets[s]
+        p_, q_, nu_c, nv_c, nu_s, nv_s = (int(x) for x in b.shapes[s])
+        assert np.array_equal(p1, pts1[o[6]:o[6] + nu_s * nv_s * 3])
+        sl = grad_slices(b, s)
+        for name, x, y in zip(("ctrl", "w", "ku", "kv"), gg, g1):
+            assert np.array_equal(x, y[sl[name]]), name
+
+
+def test_plan_gradient_mask():
+    b = uneven_subset().subset(range(10))
+    S_or, G_or = oracle_both(b, b.upstream)
+    for mask, names in ((nd.NURBS_GRAD_CTRL | nd.NURBS_GRAD_W, ("ctrl", "w")),
+                        (nd.NURBS_GRAD_KU, ("ku",)), (nd.NURBS_GRAD_KV, ("kv",))):
+        _, _, grads = plan_run(b, b.upstream, mask=mask)
+        check_grads(b, grads, G_or, names=names)
+
+
+def test_validate_flag_reports_bad_data():
+    base = uneven_subset().subset(range(6))
+    for field, code in (("w", -5), ("ku", -3), ("us", -4)):
+        b = base.subset(range(6))
+        arr = getattr(b, field)
+        if field == "w":
+            arr[3] = -1.0
+        elif field == "ku":
+            o = int(b.offsets[2, 2])
+            arr[o + 1], arr[o + 2] = 0.7, 0.2  # decreasing
+        else:
+            o = int(b.offsets[1, 4])
+            arr[o] = 1.5  # outside [0, 1]
+        sb = nd.SurfaceBatch(b.shapes, b.offsets, device=0, validate=True)
+        args = [T(getattr(b, k)) for k in ("ctrl", "w", "ku", "kv", "us", "vs")]
+        sb.forward(*args)
+        assert sb.read_device_error() == code
+        assert sb.read_device_error() == 0  # reading clears it
+    good = nd.SurfaceBatch(base.shapes, base.offsets, device=0, validate=True)
+    args = [T(getattr(base, k)) for k in ("ctrl", "w", "ku", "kv", "us", "vs")]
+    good.forward(*args)
+    good.backward(*args, T(base.upstream))
+    assert good.read_device_error() == 0
+
+
+def test_graph_replay_matches_eager():
+    b = uneven_subset().subset(range(24))
+    sb = nd.SurfaceBatch(b.shapes, b.offsets, device=0)
+    args = [T(getattr(b, k)) for k in ("ctrl", "w", "ku", "kv", "us", "vs")]
+    up = T(b.upstream)
+    pts = torch.empty(sb.n_pts_floats, dtype=torch.float32, device=dev())
+    outs = (torch.empty_like(args[0]), torch.empty_like(args[1]), torch.empty_like(args[2]),
+            torch.empty_like(args[3]))
+    sb.workspace()
+    sb.forward(*args, out=pts)
+    sb.backward(*args, up, out=outs)
+    torch.cuda.synchronize()
+    eager = [H(pts)] + [H(x) for x in outs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            sb.forward(*args, out=pts, stream=s)
+            sb.backward(*args, up, out=outs, stream=s)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        for x in [pts, *outs]:
+            x.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        got = [H(pts)] + [H(x) for x in outs]
+        for x, y in zip(got, eager):
+            assert np.array_equal(x, y)
+        sb.forward(*args)  # eager work between replays
+        torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------------
+# autograd
+# --------------------------------------------------------------------------
+
+def test_autograd_function_matches_direct_backward():
+    b = W.batch_bicubic(1, n_surf=4, nc=10, ns=50)
+    B = b.n
+    ctrl = T(b.ctrl.reshape(B, 10, 10, 3)).requires_grad_(True)
+    w = T(b.w.reshape(B, 10, 10)).requires_grad_(True)
+    ku = T(b.ku.reshape(B, -1)).requires_grad_(True)
+    kv = T(b.kv.reshape(B, -1)).requires_grad_(True)
+    us = T(b.surface(0)["us"])
+    S = nd.surface(ctrl, w, ku, kv, 3, 3, us, us)
+    tgt = T(b.target.reshape(B, 50, 50, 3))
+    ((S - tgt) ** 2).sum().backward()
+    g = (2 * (S.detach() - tgt)).contiguous()
+    direct = nd.surface_bwd(ctrl.detach(), w.detach(), ku.detach(), kv.detach(), 3, 3, us, us, g)
+    for a, d in zip((ctrl.grad, w.grad, ku.grad, kv.grad), direct):
+        assert torch.equal(a, d)
+    # only the inputs that need gradients are computed
+    ctrl2 = ctrl.detach().clone().requires_grad_(True)
+    S2 = nd.surface(ctrl2, w.detach(), ku.detach(), kv.detach(), 3, 3, us, us)
+    S2.sum().backward()
+    assert ctrl2.grad is not None
+
+
+def test_full_size_uneven_batch_sampled():
+    """The 4096-surface batch in the benchmark's launch configuration; the
+    oracle recomputes a sample of surfaces exactly."""
+    full = W.uneven_batch(3, n_surf=4096)
+    sb, pts, grads = plan_run(full, full.upstream)
+    g = np.random.Generator(np.random.PCG64(11))
+    idx = sorted(g.choice(full.n, 40, replace=False).tolist())
+    sub = full.subset(idx)
+    S_or, G_or = oracle_both(sub, sub.upstream)
+    # gather the sampled surfaces from the full results
+    got_pts = np.zeros(sub.n_pts_floats, np.float32)
+    got_g = [np.zeros(len(getattr(sub, k)), np.float32) for k in ("ctrl", "w", "ku", "kv")]
+    for new, old in enumerate(idx):
+        p, q, nu_c, nv_c, nu_s, nv_s = (int(x) for x in full.shapes[old])
+        o_new, o_old = sub.offsets[new], full.offsets[old]
+        n = nu_s * nv_s * 3
+        got_pts[o_new[6]:o_new[6] + n] = pts[o_old[6]:o_old[6] + n]
+        sl_new, sl_old = grad_slices(sub, new), grad_slices(full, old)
+        for k, name in enumerate(("ctrl", "w", "ku", "kv")):
+            got_g[k][sl_new[name]] = grads[k][sl_old[name]]
+    check_points(sub, got_pts, S_or)
+    check_grads(sub, got_g, G_or)
+    assert np.isfinite(pts).all()
