@@ -1,0 +1,237 @@
+#!/usr/bin/env python
+"""Throughput of batched NURBS surface evaluation + adjoint on one MI355X.
+
+Workload (default): the uneven batch -- 4096 surfaces, degrees p, q in 1..5,
+control sides 4..48 and sample sides 16..256 (log-uniform), non-uniform
+clamped knots with 10% repeated interior knots -- run as one ragged plan:
+one persistent forward launch, one persistent backward launch and the
+per-surface finalize.  A step is forward + backward (all four gradients)
+over the whole batch with every input resident in HBM; the upstream
+gradient dL/dS is a fixed synthetic array (see workloads.uneven_batch).
+
+Prints ONE JSON line: metric, value (surface points per second of
+forward + backward), roofline of the dominant kernel (algorithmic bytes per
+launch / its average duration, from HIP events recorded around each kernel
+during the timed steps), the FP64 oracle's throughput on a bounded sample of
+the same batch (cpu_baseline) and the parity errors of the timed outputs on
+sampled surfaces.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "surface pts/s fwd+bwd (fp32, err≤1e-5 vs fp64 oracle); p50/p99 served latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2104_14547_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(shapes):
+    """Bytes the method must move, per kernel (float32).
+
+    forward : write S (12 B/pt), read P and W (16 B/control point), read the
+              samples (4 B each) and knots (4 B each);
+    backward: read dL/dS (12 B/pt), read P and W, samples and knots;
+    finalize: write dL/dP and dL/dW (16 B/control point), dL/dU, dL/dV (4 B/knot).
+    Total 24 B/pt + 48 B/cp + 8 B/sample + 12 B/knot."""
+    import numpy as np
+    s = np.asarray(shapes, np.int64)
+    pts = int((s[:, 4] * s[:, 5]).sum())
+    cps = int((s[:, 2] * s[:, 3]).sum())
+    smp = int((s[:, 4] + s[:, 5]).sum())
+    kn = int((s[:, 2] + s[:, 0] + 1 + s[:, 3] + s[:, 1] + 1).sum())
+    return {"points": pts, "control_points": cps, "samples": smp, "knots": kn,
+            "fwd": 12 * pts + 16 * cps + 4 * smp + 4 * kn,
+            "bwd": 12 * pts + 16 * cps + 4 * smp + 4 * kn,
+            "fin": 16 * cps + 4 * kn}
+
+
+def traffic_for(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(batch, sample: int, seed: int = 17):
+    import numpy as np
+    from oracle import oracle as O
+    g = np.random.Generator(np.random.PCG64(seed))
+    idx = sorted(g.choice(batch.n, min(sample, batch.n), replace=False).tolist())
+    sub = batch.subset(idx)
+    threads = O.max_threads()
+    t0 = time.perf_counter()
+    O.fwd(sub, local=True)
+    O.bwd(sub, sub.upstream.astype(np.float64), local=True)
+    dt = time.perf_counter() - t0
+    return {"value": sub.n_points / dt, "unit": "pts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(idx)} of {batch.n} surfaces ({sub.n_points} points), FP64 oracle in "
+                      f"local (non-zero span) mode, forward + backward, {dt:.2f} s on {threads} threads"}
+
+
+def parity_sample(batch, pts, grads, n: int = 12, seed: int = 23):
+    """Max parity errors of the timed outputs on n sampled surfaces."""
+    import numpy as np
+    from oracle import oracle as O
+    g = np.random.Generator(np.random.PCG64(seed))
+    idx = sorted(g.choice(batch.n, min(n, batch.n), replace=False).tolist())
+    sub = batch.subset(idx)
+    S = O.fwd(sub, local=True)
+    G = O.bwd(sub, sub.upstream.astype(np.float64), local=True)
+    worst_p, worst_g = 0.0, 0.0
+    for new, old in enumerate(idx):
+        p, q, nu_c, nv_c, nu_s, nv_s = (int(x) for x in batch.shapes[old])
+        o_old, o_new = batch.offsets[old], sub.offsets[new]
+        npf = nu_s * nv_s * 3
+        got = pts[o_old[6]:o_old[6] + npf].astype(np.float64).reshape(-1, 3)
+        want = S[o_new[6]:o_new[6] + npf].reshape(-1, 3)
+        diag = np.linalg.norm(want.max(0) - want.min(0))
+        worst_p = max(worst_p, np.linalg.norm(got - want, axis=1).max() / diag)
+        sizes = (nu_c * nv_c * 3, nu_c * nv_c, nu_c + p + 1, nv_c + q + 1)
+        for k in range(4):
+            a = grads[k][o_old[k]:o_old[k] + sizes[k]].astype(np.float64)
+            b = G[k][o_new[k]:o_new[k] + sizes[k]]
+            worst_g = max(worst_g, np.abs(a - b).max() / np.abs(b).max())
+    return {"surfaces": len(idx), "max_point_err_rel_bbox": worst_p, "max_grad_err_rel_inf": worst_g}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="uneven_batch", choices=["uneven_batch", "batch_bicubic"])
+    ap.add_argument("--cpu-sample", type=int, default=4096, help="surfaces timed on the CPU oracle")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE={world})", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2104_14547_amd as nd
+    from paper_2104_14547_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    if args.workload == "uneven_batch":
+        batch = W.uneven_batch(3)
+    else:
+        batch = W.batch_bicubic(1)
+        batch.upstream = np.random.Generator(np.random.PCG64(9)).uniform(
+            -0.1, 0.1, batch.n_pts_floats).astype(np.float32)
+    log(f"[bench] workload {batch.name}: {batch.n} surfaces, {batch.n_points} points "
+        f"(generated in {time.perf_counter() - t0:.1f} s)")
+
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    inputs = [T(getattr(batch, k)) for k in ("ctrl", "w", "ku", "kv", "us", "vs")]
+    upstream = T(batch.upstream)
+    plan = nd.SurfaceBatch(batch.shapes, batch.offsets, device=0)
+    info = plan.info()
+    pts = torch.empty(plan.n_pts_floats, dtype=torch.float32, device=dev)
+    grads = tuple(torch.empty_like(x) for x in inputs[:4])
+    plan.workspace()
+    log(f"[bench] plan: {info}, workspace {plan.ws_bytes / 2**20:.1f} MiB")
+
+    def step():
+        plan.forward(*inputs, out=pts)
+        plan.backward(*inputs, upstream, out=grads)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_timing(args.steps)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        step()
+    end.record()
+    torch.cuda.synchronize()
+    elapsed_ms = start.elapsed_time(end)
+    kf, kb, kz = plan.read_timing()
+    plan.set_timing(0)
+    ms_step = elapsed_ms / args.steps
+    value = batch.n_points * args.steps / (elapsed_ms / 1e3)
+    log(f"[bench] {args.steps} steps in {elapsed_ms:.3f} ms: {ms_step:.4f} ms/step, {value:.4e} pts/s; "
+        f"kernels fwd {kf.mean():.4f} ms, bwd {kb.mean():.4f} ms, finalize {kz.mean():.4f} ms")
+
+    ab = algorithmic_bytes(batch.shapes)
+    avg = {"fwd": float(kf.mean()), "bwd": float(kb.mean()), "fin": float(kz.mean())}
+    names = {"fwd": "k_fwd_plan", "bwd": "k_bwd_plan", "fin": "k_fin_plan"}
+    dom = max(avg, key=avg.get)
+    achieved = ab[dom] / (avg[dom] * 1e-3) / 1e9
+    kernels = {names[k]: {"avg_ms": avg[k], "algorithmic_bytes": ab[k],
+                          "achieved_GBs": ab[k] / (avg[k] * 1e-3) / 1e9} for k in avg}
+    traffic = traffic_for(names[dom], args.workload)
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": batch.name, "surfaces": batch.n, "points": ab["points"],
+                   "control_points": ab["control_points"], "degrees": "p,q in 1..5",
+                   "launches_per_step": 3},
+        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "kernels": kernels,
+        "step_algorithmic_GBs": (ab["fwd"] + ab["bwd"] + ab["fin"]) / (ms_step * 1e-3) / 1e9,
+    }
+    if not args.no_parity:
+        t1 = time.perf_counter()
+        result["parity"] = parity_sample(batch, pts.cpu().numpy(), [g.cpu().numpy() for g in grads])
+        log(f"[bench] parity {result['parity']} ({time.perf_counter() - t1:.1f} s)")
+    if not args.no_cpu_baseline:
+        t1 = time.perf_counter()
+        result["cpu_baseline"] = cpu_baseline(batch, args.cpu_sample)
+        log(f"[bench] cpu baseline {result['cpu_baseline']['value']:.4e} pts/s "
+            f"({time.perf_counter() - t1:.1f} s)")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -177,6 +177,20 @@ int nurbs_plan_bwd(nurbs_plan *plan, const float *ctrl, const float *w,
                    float *grad_w, float *grad_ku, float *grad_kv,
                    unsigned grad_mask, void *ws, size_t ws_bytes, void *stream);
 
+/* Kernel timing of plan calls (tracing).  With max_calls > 0, every later
+ * nurbs_plan_fwd / nurbs_plan_bwd records HIP events around its kernels on
+ * the call's stream, in a ring of max_calls slots per direction; 0 turns it
+ * off.  The events are created here, never on a hot-path call.  Leave it off
+ * while capturing a graph. */
+int nurbs_plan_set_timing(nurbs_plan *plan, int max_calls);
+/* Waits for the recorded events and returns, per recorded call, the kernel
+ * durations in milliseconds: fwd[i] the forward kernel; bwd[i] the backward
+ * kernel and fin[i] the finalize kernel of backward call i.  Arrays hold at
+ * least max_calls entries (any may be NULL); *n_fwd / *n_bwd receive the
+ * number of entries written (the most recent calls, oldest first). */
+int nurbs_plan_read_timing(nurbs_plan *plan, float *fwd, int *n_fwd, float *bwd, float *fin,
+                           int *n_bwd);
+
 /* ------------------------------------------------------------------------
  * Test exports: the device span search and basis used by the kernels.
  *   knots [n_knots] (device), x [nx] (device); p in [1, NURBS_MAX_DEGREE].

@@ -37,6 +37,7 @@ EXPORTS = (
     "nurbs_status_string", "nurbs_last_error", "nurbs_ctx_device_info",
     "nurbs_surface_ws_bytes", "nurbs_surface_fwd", "nurbs_surface_bwd",
     "nurbs_plan_create", "nurbs_plan_destroy", "nurbs_plan_info", "nurbs_plan_fwd", "nurbs_plan_bwd",
+    "nurbs_plan_set_timing", "nurbs_plan_read_timing",
     "nurbs_find_spans", "nurbs_basis", "nurbs_read_device_error",
 )
 
@@ -53,6 +54,7 @@ _u = ctypes.c_uint
 _sz = ctypes.c_size_t
 _szp = ctypes.POINTER(ctypes.c_size_t)
 _ip = ctypes.POINTER(ctypes.c_int)
+_fp = ctypes.POINTER(ctypes.c_float)
 
 _SIGS = {
     "nurbs_ctx_create": (_i, [_i, ctypes.POINTER(_vp)]),
@@ -73,6 +75,8 @@ _SIGS = {
     "nurbs_plan_fwd": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "nurbs_plan_bwd": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u, _vp, _sz,
                             _vp]),
+    "nurbs_plan_set_timing": (_i, [_vp, _i]),
+    "nurbs_plan_read_timing": (_i, [_vp, _fp, _ip, _fp, _fp, _ip]),
     "nurbs_find_spans": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp]),
     "nurbs_basis": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp]),
     "nurbs_read_device_error": (_i, [_vp, _vp, _ip]),

@@ -300,6 +300,22 @@ class SurfaceBatch:
                                       ws.numel(), st), self.ctx.handle)
         return out
 
+    def set_timing(self, max_calls: int):
+        """Record HIP events around this plan's kernels (0 turns it off)."""
+        _check(N.lib().nurbs_plan_set_timing(self.handle, int(max_calls)), self.ctx.handle)
+        self._timing_slots = int(max_calls)
+
+    def read_timing(self):
+        """Per recorded call: forward, backward and finalize kernel ms."""
+        n = max(getattr(self, "_timing_slots", 0), 1)
+        f = (ctypes.c_float * n)()
+        b = (ctypes.c_float * n)()
+        z = (ctypes.c_float * n)()
+        nf, nb = ctypes.c_int(), ctypes.c_int()
+        _check(N.lib().nurbs_plan_read_timing(self.handle, f, ctypes.byref(nf), b, z, ctypes.byref(nb)),
+               self.ctx.handle)
+        return (np.array(f[:nf.value]), np.array(b[:nb.value]), np.array(z[:nb.value]))
+
     def read_device_error(self, stream=None) -> int:
         code = ctypes.c_int()
         st = stream.cuda_stream if stream is not None else _stream(self.device)

@@ -42,7 +42,22 @@ struct nurbs_plan {
     size_t ws_bytes = 0;
     int max_nU = 0, max_nV = 0;
     int maxd = 5;  // degree class of the persistent kernels (5 or 7)
+    // tracing: event ring per direction (2 events per forward, 3 per backward)
+    int trace_slots = 0;
+    std::vector<hipEvent_t> ev_f, ev_b;
+    long long calls_f = 0, calls_b = 0;
 };
+
+namespace {
+void trace_free(nurbs_plan* pl) {
+    for (hipEvent_t e : pl->ev_f) (void)hipEventDestroy(e);
+    for (hipEvent_t e : pl->ev_b) (void)hipEventDestroy(e);
+    pl->ev_f.clear();
+    pl->ev_b.clear();
+    pl->trace_slots = 0;
+    pl->calls_f = pl->calls_b = 0;
+}
+}  // namespace
 
 namespace {
 
@@ -425,6 +440,7 @@ int nurbs_plan_create(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned fl
 
 int nurbs_plan_destroy(nurbs_plan* plan) {
     if (!plan) return NURBS_OK;
+    trace_free(plan);
     if (plan->dev) (void)hipFree(plan->dev);
     delete plan;
     return NURBS_OK;
@@ -464,8 +480,15 @@ int nurbs_plan_fwd(nurbs_plan* pl, const float* ctrl, const float* w, const floa
         return fail(pl->ctx, NURBS_EWORKSPACE, "NURBS_VALIDATE needs a workspace");
     PlanArgs a = plan_args(pl, false, ws, ctrl, w, ku, kv, us, vs);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t* ev = nullptr;
+    if (pl->trace_slots > 0) {
+        ev = &pl->ev_f[2 * (size_t)(pl->calls_f % pl->trace_slots)];
+        ++pl->calls_f;
+        (void)hipEventRecord(ev[0], st);
+    }
     hipError_t e = pl->maxd == 5 ? launch_plan_fwd_d5(dim3(pl->grid_fwd), st, a, pts)
                                  : launch_plan_fwd_d7(dim3(pl->grid_fwd), st, a, pts);
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[1], st);
     if (e != hipSuccess) return hip_fail(pl->ctx, e, "launch plan forward");
     return NURBS_OK;
 }
@@ -486,15 +509,66 @@ int nurbs_plan_bwd(nurbs_plan* pl, const float* ctrl, const float* w, const floa
     PlanArgs a = plan_args(pl, true, ws, ctrl, w, ku, kv, us, vs);
     char* slots = reinterpret_cast<char*>(ws);
     hipError_t e = hipSuccess;
-    if (pl->nb > 0)
+    hipEvent_t* ev = nullptr;
+    if (pl->trace_slots > 0) {
+        ev = &pl->ev_b[3 * (size_t)(pl->calls_b % pl->trace_slots)];
+        ++pl->calls_b;
+        e = hipEventRecord(ev[0], st);
+    }
+    if (pl->nb > 0 && e == hipSuccess)
         e = pl->maxd == 5 ? launch_plan_bwd_d5(dim3(pl->grid_bwd), st, a, grad_pts, slots, grad_mask)
                           : launch_plan_bwd_d7(dim3(pl->grid_bwd), st, a, grad_pts, slots, grad_mask);
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[1], st);
     if (e == hipSuccess)
         e = pl->maxd == 5
                 ? launch_plan_fin_d5(dim3(pl->n), st, a, slots, grad_ctrl, grad_w, grad_ku, grad_kv, grad_mask)
                 : launch_plan_fin_d7(dim3(pl->n), st, a, slots, grad_ctrl, grad_w, grad_ku, grad_kv, grad_mask);
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[2], st);
     if (e != hipSuccess) return hip_fail(pl->ctx, e, "launch plan backward");
     return NURBS_OK;
+}
+
+int nurbs_plan_set_timing(nurbs_plan* pl, int max_calls) {
+    if (!pl || max_calls < 0) return fail(pl ? pl->ctx : nullptr, NURBS_EINVAL, "bad arguments");
+    trace_free(pl);
+    if (max_calls == 0) return NURBS_OK;
+    pl->ev_f.resize(2 * (size_t)max_calls);
+    pl->ev_b.resize(3 * (size_t)max_calls);
+    for (auto* v : {&pl->ev_f, &pl->ev_b})
+        for (hipEvent_t& e : *v) {
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) {
+                e = nullptr;
+                trace_free(pl);
+                return hip_fail(pl->ctx, r, "hipEventCreate");
+            }
+        }
+    pl->trace_slots = max_calls;
+    return NURBS_OK;
+}
+
+int nurbs_plan_read_timing(nurbs_plan* pl, float* fwd, int* n_fwd, float* bwd, float* fin, int* n_bwd) {
+    if (!pl) return fail(nullptr, NURBS_EINVAL, "plan is NULL");
+    if (pl->trace_slots == 0) return fail(pl->ctx, NURBS_EINVAL, "timing is off");
+    auto span = [&](std::vector<hipEvent_t>& ev, int per, long long calls, int j0, int j1, float* out,
+                    int* n) -> hipError_t {
+        const long long cnt = std::min<long long>(calls, pl->trace_slots);
+        for (long long c = 0; c < cnt; ++c) {
+            const long long call = calls - cnt + c;
+            hipEvent_t* e = &ev[per * (size_t)(call % pl->trace_slots)];
+            hipError_t r = hipEventSynchronize(e[j1]);
+            float ms = 0.f;
+            if (r == hipSuccess) r = hipEventElapsedTime(&ms, e[j0], e[j1]);
+            if (r != hipSuccess) return r;
+            if (out) out[c] = ms;
+        }
+        if (n) *n = (int)cnt;
+        return hipSuccess;
+    };
+    hipError_t r = span(pl->ev_f, 2, pl->calls_f, 0, 1, fwd, n_fwd);
+    if (r == hipSuccess) r = span(pl->ev_b, 3, pl->calls_b, 0, 1, bwd, n_bwd);
+    if (r == hipSuccess) r = span(pl->ev_b, 3, pl->calls_b, 1, 2, fin, nullptr);
+    return r ? hip_fail(pl->ctx, r, "read timing events") : NURBS_OK;
 }
 
 // --------------------------------------------------------------------------
