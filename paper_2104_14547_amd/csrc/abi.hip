@@ -88,8 +88,8 @@ int check_shape(nurbs_ctx* c, int p, int q, int nu_c, int nv_c, int nu_s, int nv
 // the same tiling -- and bitwise the same result -- alone, in a uniform
 // batch or in any ragged mix.  A tile is one wave64 over min(64, nv_s)
 // columns; the row count aims at a fixed number of points per tile.
-constexpr int kFwdTilePts = 4096;
-constexpr int kBwdTilePts = 8192;
+constexpr int kFwdTilePts = 16384;
+constexpr int kBwdTilePts = 16384;
 int tile_rows(int nu_s, int nv_s, int target_pts) {
     const int cols = std::max(1, std::min(kWave, nv_s));
     const int rows = std::max(1, target_pts / cols);

@@ -48,6 +48,23 @@ __device__ __forceinline__ float recip(float x) {
     return __builtin_fmaf(r, e, r);
 }
 
+// DPP lane moves (gfx9 encodings): quad_perm [1,0,3,2] = 0xB1,
+// quad_perm [2,3,0,1] = 0x4E, row_half_mirror = 0x141, row_mirror = 0x140.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+
+// Sum over each 16-lane DPP row; every lane of the row gets the row's sum.
+// Fixed pairing order, so the result is bitwise reproducible.
+__device__ __forceinline__ float row16_sum(float x) {
+    x += dpp_mov<0xB1>(x);
+    x += dpp_mov<0x4E>(x);
+    x += dpp_mov<0x141>(x);
+    x += dpp_mov<0x140>(x);
+    return x;
+}
+
 __device__ __forceinline__ float wave_sum(float x) {
 #pragma unroll
     for (int m = 1; m < kWave; m <<= 1) x += __shfl_xor(x, m, kWave);

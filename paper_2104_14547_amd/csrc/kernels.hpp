@@ -68,12 +68,6 @@ __device__ __forceinline__ SlotView slot_view(char* base, int p, int nu_c, int n
     return v;
 }
 
-// per-wave LDS scratch of the backward tile
-struct BwdLds {
-    float4 col[kWave * (kMaxDeg + 1)];  // segment sums, [head lane][h]
-    int head_of[kWG];                   // key offset -> head lane, or -1
-};
-
 // device error word (first error wins)
 __device__ __forceinline__ void post_error(int* err, int code) {
     if (err) atomicCAS(err, 0, code);
@@ -109,37 +103,173 @@ __device__ __forceinline__ void validate_surface(const Surf& s, int P, int Q, in
 }
 
 // --------------------------------------------------------------------------
-// forward tile
+// control-row ring: the rows of the u-window (and the next one) for the
+// tile's control columns j0 .. j0+ncols-1, as homogeneous points in LDS
 // --------------------------------------------------------------------------
-template <int P, int QM>
-__device__ __forceinline__ void fwd_tile(const Surf& s, int q, int col0, int row0, int row1, float* __restrict__ pts) {
+constexpr int kRingCap = 384;  // float4 entries per wave (6 KiB)
+constexpr int kEBatch = 16;    // rows per batched reduction of dL/dN(u)
+
+struct Ring {
+    float4* base;  // LDS, kRingCap entries
+    int j0, ncols, nslots;
+    bool on;       // false: the tile's column range does not fit, read Pw from global
+};
+
+__device__ __forceinline__ float4* ring_row(const Ring& rg, int i) { return rg.base + (i % rg.nslots) * rg.ncols; }
+
+// Lanes load control row i (columns j0 .. j0+ncols-1) into registers; the
+// ring stores them later, so the load latency overlaps other work.
+struct RowPrefetch {
+    float4 v;  // column j0 + lane (the ring holds at most 64 columns)
+};
+
+__device__ __forceinline__ void prefetch_row(const Surf& s, const Ring& rg, int i, RowPrefetch& pf) {
+    const int lane = lane_id();
+    if (i < s.nu_c && lane < rg.ncols) pf.v = load_pw(s, i, rg.j0 + lane);
+}
+
+__device__ __forceinline__ void store_row(const Ring& rg, int i, const RowPrefetch& pf) {
+    const int lane = lane_id();
+    if (lane < rg.ncols) ring_row(rg, i)[lane] = pf.v;
+}
+
+// R_i(b) for this lane's column from the ring (or from global memory).
+template <int QM>
+__device__ __forceinline__ float4 ring_contract(const Surf& s, const Ring& rg, int i, int jb,
+                                                const float Nv[QM + 1], int q) {
+    if (!rg.on) return row_contract<QM>(s, i, jb, Nv, q);
+    const float4* row = ring_row(rg, i) + (jb - rg.j0);
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int h = 0; h <= QM; ++h)
+        if (h <= q) acc = fma4(Nv[h], row[h], acc);
+    return acc;
+}
+
+// Column set-up shared by forward and backward: this lane's v-span and
+// basis, and the tile's control-column range [j0, j0 + ncols).
+template <int QM>
+__device__ __forceinline__ int tile_columns(const Surf& s, int q, int col0, float Nv[QM + 1], bool& act,
+                                            int& j0, int& ncols) {
     const int lane = lane_id();
     const int b = col0 + lane;
-    const bool act = b < s.nv_s;
-    float Nv[QM + 1];
+    act = b < s.nv_s;
     const int kb = sample_basis_rt<QM>(s.kv, s.nv_c, s.vs[act ? b : s.nv_s - 1], q, Nv);
+    const int nact = min(kWave, s.nv_s - col0);
+    const int kfirst = bcast_lane(kb, 0);
+    const int klast = bcast_lane(kb, nact - 1);
+    j0 = kfirst - q;
+    ncols = klast - j0 + 1;
+    return kb;
+}
+
+// Copy a knot vector (<= kWG entries) into this wave's LDS, so that span
+// searches and basis evaluations read LDS instead of chasing global loads.
+__device__ __forceinline__ const float* stage_knots(const float* __restrict__ U, int n, float* dst) {
+    const int lane = lane_id();
+    float v[kWG / kWave];
+#pragma unroll
+    for (int m = 0; m < kWG / kWave; ++m) {
+        const int i = lane + m * kWave;
+        if (i < n) v[m] = U[i];
+    }
+#pragma unroll
+    for (int m = 0; m < kWG / kWave; ++m) {
+        const int i = lane + m * kWave;
+        if (i < n) dst[i] = v[m];
+    }
+    return dst;
+}
+
+// The first P+2 ring rows (window rows k-P .. k and the next one), loads
+// issued together so the tile waits for one memory latency, not P+2.
+template <int P>
+__device__ __forceinline__ void stage_ring(const Surf& s, const Ring& rg, int k) {
+    const int lane = lane_id();
+    float4 v[P + 2];
+#pragma unroll
+    for (int r = 0; r < P + 2; ++r) {
+        const int i = k - P + r;
+        if (i < s.nu_c && lane < rg.ncols) v[r] = load_pw(s, i, rg.j0 + lane);
+    }
+#pragma unroll
+    for (int r = 0; r < P + 2; ++r)
+        if (lane < rg.ncols) ring_row(rg, k - P + r)[lane] = v[r];
+}
+
+__device__ __forceinline__ Ring make_ring(float4* base, int j0, int ncols, int p) {
+    Ring rg;
+    rg.base = base;
+    rg.j0 = j0;
+    rg.ncols = ncols;
+    rg.nslots = p + 2;
+    rg.on = ncols <= kWave && (p + 2) * ncols <= kRingCap;
+    return rg;
+}
+
+// --------------------------------------------------------------------------
+// forward tile
+// --------------------------------------------------------------------------
+// per-wave LDS of the forward tile
+struct FwdLds {
+    float4 ring[kRingCap];
+    float knots[2][kWG];
+};
+
+template <int P, int QM>
+__device__ __forceinline__ void fwd_tile(const Surf& sg, int q, int col0, int row0, int row1,
+                                         float* __restrict__ pts, FwdLds* lds) {
+    const int lane = lane_id();
+    const int b = col0 + lane;
+    // knots from LDS from here on
+    Surf s = sg;
+    s.ku = stage_knots(sg.ku, sg.nu_c + P + 1, lds->knots[0]);
+    s.kv = stage_knots(sg.kv, sg.nv_c + q + 1, lds->knots[1]);
+    wave_lds_sync();
+    float4* ring_lds = lds->ring;
+    float Nv[QM + 1];
+    bool act;
+    int j0, ncols;
+    const int kb = tile_columns<QM>(s, q, col0, Nv, act, j0, ncols);
     const int jb = kb - q;
+    const Ring rg = make_ring(ring_lds, j0, ncols, P);
 
     float4 R[P + 1];
-    int cur = -1;  // span of the window (rows cur-P .. cur); -1 = empty
+    RowPrefetch pf;
+    int cur = -1;  // window rows cur-P .. cur; ring holds rows up to nxt-1
+    int nxt = 0;
+    float u_next = s.us[min(row0 + lane, row1 - 1)];
     for (int a0 = row0; a0 < row1; a0 += kWave) {
         const int nr = min(kWave, row1 - a0);
         float Nu_l[P + 1];
-        const int ka_l = sample_basis<P>(s.ku, s.nu_c, s.us[a0 + min(lane, nr - 1)], Nu_l);
+        const int ka_l = sample_basis<P>(s.ku, s.nu_c, u_next, Nu_l);
+        if (a0 + kWave < row1) u_next = s.us[min(a0 + kWave + lane, row1 - 1)];
         for (int t = 0; t < nr; ++t) {
             const int ka = bcast_lane(ka_l, t);
-            if (ka != cur) {
-                if (cur >= 0 && ka > cur && ka - cur <= P) {
-                    do {
+            if (cur < 0) {
+                // first row: stage rows ka-P .. ka+1, prefetch ka+2
+                if (rg.on) {
+                    stage_ring<P>(s, rg, ka);
+                    wave_lds_sync();
+                    nxt = ka + 2;
+                    prefetch_row(s, rg, nxt, pf);
+                }
+                cur = ka;
 #pragma unroll
-                        for (int r = 0; r < P; ++r) R[r] = R[r + 1];
-                        ++cur;
-                        R[P] = row_contract<QM>(s, cur, jb, Nv, q);
-                    } while (cur < ka);
-                } else {
-                    cur = ka;
+                for (int r = 0; r <= P; ++r) R[r] = ring_contract<QM>(s, rg, ka - P + r, jb, Nv, q);
+            } else {
+                while (cur < ka) {
 #pragma unroll
-                    for (int r = 0; r <= P; ++r) R[r] = row_contract<QM>(s, ka - P + r, jb, Nv, q);
+                    for (int r = 0; r < P; ++r) R[r] = R[r + 1];
+                    ++cur;
+                    R[P] = ring_contract<QM>(s, rg, cur, jb, Nv, q);
+                    if (rg.on) {
+                        wave_lds_sync();
+                        store_row(rg, nxt, pf);  // replaces row cur-P-1, now outside the window
+                        wave_lds_sync();
+                        ++nxt;
+                        prefetch_row(s, rg, nxt, pf);
+                    }
                 }
             }
             float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -174,49 +304,79 @@ struct BwdState {
     float f[QM + 1];  // dL/dNv_h(v_b) partial
 };
 
-// Flush control row i (accumulator G) of the tile: dV partial and the
-// rect row i - i0 of dL/dPw.
+// per-wave LDS of the backward tile, sized for degrees p <= PM, q <= QM
+template <int PM, int QM>
+struct BwdLdsT {
+    float knots[2][kWG];
+    float4 ring[kRingCap];
+    float4 col[kWave * (QM + 1)];           // segment sums, [head lane][h]
+    short head_of[kWG];                     // key offset -> head lane, or -1
+    float ebuf[kEBatch * 4 * (PM + 1)];     // 16-lane partials of dL/dNu
+};
+
+// pointers into one wave's BwdLdsT
+struct BwdLds {
+    float* knots[2];
+    float4* ring;
+    float4* col;
+    short* head_of;
+    float* ebuf;
+};
+
+template <int PM, int QM>
+__device__ __forceinline__ BwdLds bwd_lds(BwdLdsT<PM, QM>* t) {
+    BwdLds l;
+    l.knots[0] = t->knots[0];
+    l.knots[1] = t->knots[1];
+    l.ring = t->ring;
+    l.col = t->col;
+    l.head_of = t->head_of;
+    l.ebuf = t->ebuf;
+    return l;
+}
+
+// Flush control row i (accumulator G) of the tile: dV partial and the rect
+// row i - i0 of dL/dPw.
 template <int QM>
-__device__ __forceinline__ void flush_row(const Surf& s, BwdState<QM>& st, int i, int i0, float4 G,
-                                          float4* __restrict__ rect, BwdLds* L, bool want_pw,
+__device__ __forceinline__ void flush_row(const Surf& s, BwdState<QM>& st, const Ring& rg, int i, int i0,
+                                          float4 G, float4* __restrict__ rect, BwdLds* L, bool want_pw,
                                           bool want_kv) {
     const int lane = lane_id();
     const int q = st.q;
     if (want_kv) {
+        if (rg.on) {
+            const float4* row = ring_row(rg, i) + (st.jb - rg.j0);
 #pragma unroll
-        for (int h = 0; h <= QM; ++h)
-            if (h <= q) st.f[h] += dot4(load_pw(s, i, st.jb + h), G);
-    }
-    if (!want_pw) return;
-    float4 x[QM + 1];
+            for (int h = 0; h <= QM; ++h)
+                if (h <= q) st.f[h] += dot4(row[h], G);
+        } else {
 #pragma unroll
-    for (int h = 0; h <= QM; ++h) {
-        const float c = st.act ? st.Nv[h] : 0.f;
-        x[h] = make_float4(c * G.x, c * G.y, c * G.z, c * G.w);
-    }
-    // segmented inclusive scan over lanes sharing a v-span
-    for (int step = 0, d = 1; step < st.nsteps; ++step, d <<= 1) {
-        const bool take = (lane - d) >= st.seg_first;
-#pragma unroll
-        for (int h = 0; h <= QM; ++h) {
-            if (h > q) continue;
-            float4 y;
-            y.x = __shfl_up(x[h].x, d, kWave);
-            y.y = __shfl_up(x[h].y, d, kWave);
-            y.z = __shfl_up(x[h].z, d, kWave);
-            y.w = __shfl_up(x[h].w, d, kWave);
-            if (take) {
-                x[h].x += y.x;
-                x[h].y += y.y;
-                x[h].z += y.z;
-                x[h].w += y.w;
-            }
+            for (int h = 0; h <= QM; ++h)
+                if (h <= q) st.f[h] += dot4(load_pw(s, i, st.jb + h), G);
         }
     }
-    if (st.head) {
+    if (!want_pw) return;
+    // segmented inclusive scan over lanes sharing a v-span, one h at a time
 #pragma unroll
-        for (int h = 0; h <= QM; ++h)
-            if (h <= q) L->col[lane * (QM + 1) + h] = x[h];
+    for (int h = 0; h <= QM; ++h) {
+        if (h > q) continue;
+        const float c = st.act ? st.Nv[h] : 0.f;
+        float4 x = make_float4(c * G.x, c * G.y, c * G.z, c * G.w);
+        for (int step = 0, d = 1; step < st.nsteps; ++step, d <<= 1) {
+            const bool take = (lane - d) >= st.seg_first;
+            float4 y;
+            y.x = __shfl_up(x.x, d, kWave);
+            y.y = __shfl_up(x.y, d, kWave);
+            y.z = __shfl_up(x.z, d, kWave);
+            y.w = __shfl_up(x.w, d, kWave);
+            if (take) {
+                x.x += y.x;
+                x.y += y.y;
+                x.z += y.z;
+                x.w += y.w;
+            }
+        }
+        if (st.head) L->col[lane * (QM + 1) + h] = x;
     }
     wave_lds_sync();
     // control column j = j0 + c gathers keys kfirst + c - h
@@ -225,7 +385,7 @@ __device__ __forceinline__ void flush_row(const Surf& s, BwdState<QM>& st, int i
 #pragma unroll
         for (int h = 0; h <= QM; ++h) {
             const int o = c - h;
-            const int hl = (h <= q && o >= 0 && o < st.nkeys) ? L->head_of[o] : -1;
+            const int hl = (h <= q && o >= 0 && o < st.nkeys) ? (int)L->head_of[o] : -1;
             if (hl >= 0) {
                 const float4 v = L->col[hl * (QM + 1) + h];
                 acc.x += v.x;
@@ -245,24 +405,20 @@ template <int QM>
 __device__ __forceinline__ void bwd_columns(const Surf& s, int q, int col0, BwdState<QM>& st, BwdLds* L) {
     const int lane = lane_id();
     st.q = q;
-    const int b = col0 + lane;
-    st.act = b < s.nv_s;
-    st.kb = sample_basis_rt<QM>(s.kv, s.nv_c, s.vs[st.act ? b : s.nv_s - 1], q, st.Nv);
+    int j0, ncols;
+    st.kb = tile_columns<QM>(s, q, col0, st.Nv, st.act, j0, ncols);
     st.jb = st.kb - q;
 #pragma unroll
     for (int h = 0; h <= QM; ++h) st.f[h] = 0.f;
-
-    // segment structure of the columns (spans are non-decreasing in b)
-    const int nact = min(kWave, s.nv_s - col0);
-    const int kfirst = bcast_lane(st.kb, 0);
-    const int klast = bcast_lane(st.kb, nact - 1);
-    st.nkeys = klast - kfirst + 1;
-    st.j0 = kfirst - q;
-    st.ncols = klast - st.j0 + 1;
+    const int kfirst = j0 + q;
+    st.j0 = j0;
+    st.ncols = ncols;
+    st.nkeys = ncols - q;
     st.key_off = st.kb - kfirst;
+    const int nact = min(kWave, s.nv_s - col0);
     const int kb_next = __shfl_down(st.kb, 1, kWave);
     st.head = st.act && (lane == nact - 1 || kb_next != st.kb);
-    {   // first lane of the segment: max over lanes <= me with a different key, +1
+    {   // first lane of the segment: the largest segment start at or below this lane
         const int kb_prev = __shfl_up(st.kb, 1, kWave);
         const bool starts = st.act && (lane == 0 || kb_prev != st.kb);
         int f = starts ? lane : 0;
@@ -279,29 +435,47 @@ __device__ __forceinline__ void bwd_columns(const Surf& s, int q, int col0, BwdS
         while ((1 << steps) < len) ++steps;
         st.nsteps = steps;
     }
-    for (int o = lane; o < st.nkeys; o += kWave) L->head_of[o] = -1;
+    for (int o = lane; o < st.nkeys; o += kWave) L->head_of[o] = (short)-1;
     wave_lds_sync();
-    if (st.head) L->head_of[st.key_off] = lane;
+    if (st.head) L->head_of[st.key_off] = (short)lane;
+    wave_lds_sync();
+}
+
+// Finish a batch of nb rows of dL/dNu: add the four 16-lane partials of
+// each (row, r) in a fixed order and store them contiguously.
+template <int P>
+__device__ __forceinline__ void flush_e(BwdLds* L, int nb, float* __restrict__ e_out) {
+    const int lane = lane_id();
+    wave_lds_sync();
+    for (int idx = lane; idx < nb * (P + 1); idx += kWave) {
+        const int t = idx / (P + 1), r = idx - t * (P + 1);
+        const float* e = L->ebuf + (t * 4) * (P + 1) + r;
+        e_out[idx] = ((e[0] + e[P + 1]) + e[2 * (P + 1)]) + e[3 * (P + 1)];
+    }
     wave_lds_sync();
 }
 
 template <int P, int QM>
 __device__ __forceinline__ void bwd_rows(const Surf& s, BwdState<QM>& st, int col0, int row0, int row1,
-                         const float* __restrict__ gpts, SlotView out, BwdLds* L, unsigned mask) {
+                                         const float* __restrict__ gpts, SlotView out, BwdLds* L,
+                                         unsigned mask) {
+    constexpr int D = 4;  // rows of dL/dS in flight
     const int lane = lane_id();
     const bool want_pw = (mask & 3u) != 0;
     const bool want_ku = (mask & 4u) != 0;
     const bool want_kv = (mask & 8u) != 0;
     const int q = st.q;
     const int b = col0 + lane;
+    const Ring rg = make_ring(L->ring, st.j0, st.ncols, P);
     float4 R[P + 1], G[P + 1];
-    int cur = -1, i0 = 0;
+    RowPrefetch pf;
+    int cur = -1, i0 = 0, nxt = 0;
     // Slide the window until its last row is `target`, flushing every row
     // that leaves it.  Rows past the last control row are never loaded; the
     // end-of-tile drain uses this with target = cur + P + 1.
     auto advance = [&](int target) {
         while (cur < target) {
-            flush_row<QM>(s, st, cur - P, i0, G[0], out.rect, L, want_pw, want_kv);
+            flush_row<QM>(s, st, rg, cur - P, i0, G[0], out.rect, L, want_pw, want_kv);
 #pragma unroll
             for (int r = 0; r < P; ++r) {
                 R[r] = R[r + 1];
@@ -309,59 +483,88 @@ __device__ __forceinline__ void bwd_rows(const Surf& s, BwdState<QM>& st, int co
             }
             ++cur;
             G[P] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (cur < s.nu_c) R[P] = row_contract<QM>(s, cur, st.jb, st.Nv, q);
+            if (cur < s.nu_c) R[P] = ring_contract<QM>(s, rg, cur, st.jb, st.Nv, q);
+            if (rg.on && nxt < s.nu_c) {
+                wave_lds_sync();
+                store_row(rg, nxt, pf);  // replaces the row just flushed
+                wave_lds_sync();
+                ++nxt;
+                prefetch_row(s, rg, nxt, pf);
+            }
         }
     };
+    // dL/dS of the next D rows, in flight while the current rows are processed
+    float3 gq[D];
+    auto load_g = [&](int a) {
+        float3 v = make_float3(0.f, 0.f, 0.f);
+        if (st.act && a < row1) {
+            const float* gp = gpts + 3 * ((size_t)a * s.nv_s + b);
+            v = make_float3(gp[0], gp[1], gp[2]);
+        }
+        return v;
+    };
+#pragma unroll
+    for (int j = 0; j < D; ++j) gq[j] = load_g(row0 + j);
+    float u_next = s.us[min(row0 + lane, row1 - 1)];
     for (int a0 = row0; a0 < row1; a0 += kWave) {
         const int nr = min(kWave, row1 - a0);
         float Nu_l[P + 1];
-        const int ka_l = sample_basis<P>(s.ku, s.nu_c, s.us[a0 + min(lane, nr - 1)], Nu_l);
-        for (int t = 0; t < nr; ++t) {
-            const int ka = bcast_lane(ka_l, t);
-            if (cur < 0) {
-                cur = ka;
-                i0 = ka - P;
+        const int ka_l = sample_basis<P>(s.ku, s.nu_c, u_next, Nu_l);
+        if (a0 + kWave < row1) u_next = s.us[min(a0 + kWave + lane, row1 - 1)];
+        int eb = 0;  // rows in the current dL/dNu batch
+        for (int t0 = 0; t0 < nr; t0 += D) {
 #pragma unroll
-                for (int r = 0; r <= P; ++r) {
-                    R[r] = row_contract<QM>(s, ka - P + r, st.jb, st.Nv, q);
-                    G[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int j = 0; j < D; ++j) {
+                const int t = t0 + j;
+                if (t >= nr) break;
+                const int ka = bcast_lane(ka_l, t);
+                if (cur < 0) {
+                    cur = ka;
+                    i0 = ka - P;
+                    if (rg.on) {
+                        stage_ring<P>(s, rg, ka);
+                        wave_lds_sync();
+                        nxt = ka + 2;
+                        prefetch_row(s, rg, nxt, pf);
+                    }
+#pragma unroll
+                    for (int r = 0; r <= P; ++r) {
+                        R[r] = ring_contract<QM>(s, rg, ka - P + r, st.jb, st.Nv, q);
+                        G[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+                } else {
+                    // rows are non-decreasing, so the window only moves forward
+                    advance(ka);
                 }
-            } else {
-                // rows are non-decreasing, so the window only moves forward
-                advance(ka);
-            }
-            float Nu[P + 1];
+                const float3 g = gq[j];
+                gq[j] = load_g(a0 + t + D);
+                float Nu[P + 1];
 #pragma unroll
-            for (int r = 0; r <= P; ++r) Nu[r] = bcast_lane(Nu_l[r], t);
-            // recompute S' (nothing is saved by the forward)
-            float4 sp = make_float4(0.f, 0.f, 0.f, 0.f);
+                for (int r = 0; r <= P; ++r) Nu[r] = bcast_lane(Nu_l[r], t);
+                // recompute S' (nothing is saved by the forward)
+                float4 sp = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-            for (int r = 0; r <= P; ++r) sp = fma4(Nu[r], R[r], sp);
-            const float rw = recip(sp.w);
-            float gx = 0.f, gy = 0.f, gz = 0.f;
-            if (st.act) {
-                const float* gp = gpts + 3 * ((size_t)(a0 + t) * s.nv_s + b);
-                gx = gp[0];
-                gy = gp[1];
-                gz = gp[2];
-            }
-            const float cx = gx * rw, cy = gy * rw, cz = gz * rw;
-            const float cw = -(cx * sp.x + cy * sp.y + cz * sp.z) * rw;
-            const float4 hv = make_float4(cx, cy, cz, cw);
+                for (int r = 0; r <= P; ++r) sp = fma4(Nu[r], R[r], sp);
+                const float rw = recip(sp.w);
+                const float cx = g.x * rw, cy = g.y * rw, cz = g.z * rw;
+                const float cw = -(cx * sp.x + cy * sp.y + cz * sp.z) * rw;
+                const float4 hv = make_float4(cx, cy, cz, cw);
 #pragma unroll
-            for (int r = 0; r <= P; ++r) G[r] = fma4(Nu[r], hv, G[r]);
-            if (want_ku) {
-                float E[P + 1];
+                for (int r = 0; r <= P; ++r) G[r] = fma4(Nu[r], hv, G[r]);
+                if (want_ku) {
 #pragma unroll
-                for (int r = 0; r <= P; ++r) E[r] = wave_sum(dot4(R[r], hv));
-                if (lane <= P) {
-                    float v = E[0];
-#pragma unroll
-                    for (int r = 1; r <= P; ++r) v = (lane == r) ? E[r] : v;
-                    out.e[(size_t)(a0 + t - row0) * (P + 1) + lane] = v;
+                    for (int r = 0; r <= P; ++r) {
+                        const float e = row16_sum(dot4(R[r], hv));
+                        if ((lane & 15) == 0) L->ebuf[(eb * 4 + (lane >> 4)) * (P + 1) + r] = e;
+                    }
+                    if (++eb == kEBatch) {
+                        flush_e<P>(L, eb, out.e + (size_t)(a0 + t + 1 - eb - row0) * (P + 1));
+                        eb = 0;
+                    }
                 }
             }
         }
+        if (want_ku && eb > 0) flush_e<P>(L, eb, out.e + (size_t)(a0 + nr - eb - row0) * (P + 1));
     }
     // flush the rows still in the window
     const int i1 = cur;
@@ -379,9 +582,19 @@ __device__ __forceinline__ void bwd_rows(const Surf& s, BwdState<QM>& st, int co
     }
 }
 
+// Knots of the tile's surface into LDS; returns the surface view that reads them.
+__device__ __forceinline__ Surf bwd_stage_knots(const Surf& sg, int p, int q, BwdLds* L) {
+    Surf s = sg;
+    s.ku = stage_knots(sg.ku, sg.nu_c + p + 1, L->knots[0]);
+    s.kv = stage_knots(sg.kv, sg.nv_c + q + 1, L->knots[1]);
+    wave_lds_sync();
+    return s;
+}
+
 template <int P, int QM>
-__device__ __forceinline__ void bwd_tile(const Surf& s, int q, int col0, int row0, int row1,
-                         const float* __restrict__ gpts, SlotView out, BwdLds* L, unsigned mask) {
+__device__ __forceinline__ void bwd_tile(const Surf& sg, int q, int col0, int row0, int row1,
+                                         const float* __restrict__ gpts, SlotView out, BwdLds* L, unsigned mask) {
+    const Surf s = bwd_stage_knots(sg, P, q, L);
     BwdState<QM> st;
     bwd_columns<QM>(s, q, col0, st, L);
     bwd_rows<P, QM>(s, st, col0, row0, row1, gpts, out, L, mask);
@@ -390,13 +603,18 @@ __device__ __forceinline__ void bwd_tile(const Surf& s, int q, int col0, int row
 // --------------------------------------------------------------------------
 // finalize: one workgroup (kWG threads) per surface
 // --------------------------------------------------------------------------
+constexpr int kFinMaxTiles = 256;  // tile headers staged in LDS (more: read from global)
+constexpr int kFinCp = 8;          // control points per thread per pass
+
 struct FinLds {
-    double contrib[kWG * (2 * kMaxDeg + 2)];  // per sample, knot-window adjoints
-    int span[kWG];                            // span of each sample of the chunk
+    float knots[kWG];
+    int4 hdr[kFinMaxTiles];
+    float contrib[kWG * (2 * kMaxDeg + 2)];  // per sample, knot-window adjoints
+    int span[kWG];
 };
 
-// Tiles of one surface in their fixed summation order: slot pointer,
-// column start and row range of tile t.
+// Tiles of one surface in natural order (row blocks outer, 64-column blocks
+// inner): slot pointer, column start and row range of tile t.
 struct TileRef {
     const char* slot;
     int col0, row0, row1;
@@ -405,15 +623,19 @@ struct TileRef {
 
 // Knot gradient of one direction: for every sample x_a of the direction,
 // coef(a)[r] = dL/dN_{k_a-D+r}(x_a) is turned into per-knot adjoints by
-// basis_knot_adjoint; the adjoints are then summed over samples in sample
-// order (chunks of kWG samples staged in LDS), one thread per knot.
+// basis_knot_adjoint (FP64); the adjoints are then summed over samples in
+// sample order (chunks of kWG samples staged in LDS), one thread per knot.
 template <int D, class CoefAt>
-__device__ __forceinline__ void knot_gradient(const float* __restrict__ U, int nc, const float* __restrict__ xs, int ns,
-                              CoefAt coef_at, float* __restrict__ gout, FinLds* L) {
+__device__ __forceinline__ void knot_gradient(const float* __restrict__ Ug, int nc, const float* __restrict__ xs,
+                                              int ns, CoefAt coef_at, float* __restrict__ gout, FinLds* L) {
     constexpr int W = 2 * D + 2;
     const int tid = threadIdx.x;
     const int nk = nc + D + 1;
     const int n = nc - 1;
+    __syncthreads();
+    if (tid < nk) L->knots[tid] = Ug[tid];
+    __syncthreads();
+    const float* U = L->knots;
     double acc = 0.0;
     for (int a0 = 0; a0 < ns; a0 += kWG) {
         const int a = a0 + tid;
@@ -426,7 +648,7 @@ __device__ __forceinline__ void knot_gradient(const float* __restrict__ U, int n
             double g[W];
             basis_knot_adjoint<D>(U, k, x, e, g);
 #pragma unroll
-            for (int t = 0; t < W; ++t) L->contrib[tid * W + t] = g[t];
+            for (int t = 0; t < W; ++t) L->contrib[tid * W + t] = (float)g[t];
         }
         L->span[tid] = k;
         __syncthreads();
@@ -434,7 +656,7 @@ __device__ __forceinline__ void knot_gradient(const float* __restrict__ U, int n
         if (tid < nk) {
             for (int r = 0; r < cnt; ++r) {
                 const int t = tid - (L->span[r] - D);
-                if (t >= 0 && t < W) acc += L->contrib[r * W + t];
+                if (t >= 0 && t < W) acc += (double)L->contrib[r * W + t];
             }
         }
         __syncthreads();
@@ -444,67 +666,90 @@ __device__ __forceinline__ void knot_gradient(const float* __restrict__ U, int n
 
 template <int P, int Q, class TileAt>
 __device__ __forceinline__ void finalize_surface(const Surf& s, int ntiles, TileAt tile_at, float* __restrict__ gctrl,
-                                 float* __restrict__ gw, float* __restrict__ gku, float* __restrict__ gkv,
-                                 unsigned mask, FinLds* L) {
+                                                 float* __restrict__ gw, float* __restrict__ gku,
+                                                 float* __restrict__ gkv, unsigned mask, FinLds* L) {
     const int tid = threadIdx.x;
     const size_t rect_bytes = 16 * (size_t)s.nu_c * s.nv_c;
+    const int ncb = (s.nv_s + kWave - 1) / kWave;
+    const int rows = ntiles > 0 ? tile_at(0).alloc_rows : 1;
+    const int nrb = ncb > 0 ? ntiles / ncb : 0;
+    const bool hdr_lds = ntiles <= kFinMaxTiles;
+    if (hdr_lds)
+        for (int t = tid; t < ntiles; t += kWG) L->hdr[t] = *reinterpret_cast<const int4*>(tile_at(t).slot);
+    __syncthreads();
     // dL/dP and dL/dw from the tile rectangles, tiles in fixed order
     if (mask & 3u) {
-        for (int ij = tid; ij < s.nu_c * s.nv_c; ij += kWG) {
-            const int i = ij / s.nv_c, j = ij - i * s.nv_c;
-            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int ncp = s.nu_c * s.nv_c;
+        for (int base = 0; base < ncp; base += kWG * kFinCp) {
+            float4 acc[kFinCp];
+            int ii[kFinCp], jj[kFinCp];
+#pragma unroll
+            for (int c = 0; c < kFinCp; ++c) {
+                acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+                const int ij = base + c * kWG + tid;
+                ii[c] = ij / s.nv_c;
+                jj[c] = ij - ii[c] * s.nv_c;
+            }
             for (int t = 0; t < ntiles; ++t) {
-                const TileRef tr = tile_at(t);
-                const int* hdr = reinterpret_cast<const int*>(tr.slot);
-                const int i0 = hdr[0], i1 = hdr[1], j0 = hdr[2], j1 = hdr[3];
-                if (i >= i0 && i <= i1 && j >= j0 && j <= j1) {
-                    const float4 v = reinterpret_cast<const float4*>(tr.slot + 16)[(size_t)(i - i0) * (j1 - j0 + 1) + (j - j0)];
-                    acc.x += v.x;
-                    acc.y += v.y;
-                    acc.z += v.z;
-                    acc.w += v.w;
+                const char* slot = tile_at(t).slot;
+                const int4 h = hdr_lds ? L->hdr[t] : *reinterpret_cast<const int4*>(slot);
+                const float4* rect = reinterpret_cast<const float4*>(slot + 16);
+                const int pitch = h.w - h.z + 1;
+#pragma unroll
+                for (int c = 0; c < kFinCp; ++c) {
+                    const int ij = base + c * kWG + tid;
+                    if (ij < ncp && ii[c] >= h.x && ii[c] <= h.y && jj[c] >= h.z && jj[c] <= h.w) {
+                        const float4 v = rect[(size_t)(ii[c] - h.x) * pitch + (jj[c] - h.z)];
+                        acc[c].x += v.x;
+                        acc[c].y += v.y;
+                        acc[c].z += v.z;
+                        acc[c].w += v.w;
+                    }
                 }
             }
-            const float wt = s.w[ij];
-            const float* pc = s.ctrl + 3 * ij;
-            if (mask & 1u) {
-                gctrl[3 * ij + 0] = wt * acc.x;
-                gctrl[3 * ij + 1] = wt * acc.y;
-                gctrl[3 * ij + 2] = wt * acc.z;
+#pragma unroll
+            for (int c = 0; c < kFinCp; ++c) {
+                const int ij = base + c * kWG + tid;
+                if (ij >= ncp) continue;
+                const float wt = s.w[ij];
+                const float* pc = s.ctrl + 3 * ij;
+                if (mask & 1u) {
+                    gctrl[3 * ij + 0] = wt * acc[c].x;
+                    gctrl[3 * ij + 1] = wt * acc[c].y;
+                    gctrl[3 * ij + 2] = wt * acc[c].z;
+                }
+                if (mask & 2u) gw[ij] = pc[0] * acc[c].x + pc[1] * acc[c].y + pc[2] * acc[c].z + acc[c].w;
             }
-            if (mask & 2u) gw[ij] = pc[0] * acc.x + pc[1] * acc.y + pc[2] * acc.z + acc.w;
         }
     }
-    // dL/dU: e(a) = sum over the column tiles covering row a
+    // dL/dU: e(a) = sum over the column blocks of a's row block
     if (mask & 4u) {
         auto coef = [&](int a, double e[P + 1]) {
 #pragma unroll
             for (int r = 0; r <= P; ++r) e[r] = 0.0;
-            for (int t = 0; t < ntiles; ++t) {
-                const TileRef tr = tile_at(t);
-                if (a >= tr.row0 && a < tr.row1) {
-                    const float* ev = reinterpret_cast<const float*>(tr.slot + 16 + rect_bytes) +
-                                      (size_t)(a - tr.row0) * (P + 1);
+            const int rb = a / rows;
+            for (int cb = 0; cb < ncb; ++cb) {
+                const TileRef tr = tile_at(rb * ncb + cb);
+                const float* ev = reinterpret_cast<const float*>(tr.slot + 16 + rect_bytes) +
+                                  (size_t)(a - tr.row0) * (P + 1);
 #pragma unroll
-                    for (int r = 0; r <= P; ++r) e[r] += (double)ev[r];
-                }
+                for (int r = 0; r <= P; ++r) e[r] += (double)ev[r];
             }
         };
         knot_gradient<P>(s.ku, s.nu_c, s.us, s.nu_s, coef, gku, L);
     }
-    // dL/dV: f(b) = sum over the row tiles covering column b
+    // dL/dV: f(b) = sum over the row blocks of b's column block
     if (mask & 8u) {
         auto coef = [&](int b, double f[Q + 1]) {
 #pragma unroll
             for (int h = 0; h <= Q; ++h) f[h] = 0.0;
-            for (int t = 0; t < ntiles; ++t) {
-                const TileRef tr = tile_at(t);
-                if (b >= tr.col0 && b < tr.col0 + kWave) {
-                    const float* fv = reinterpret_cast<const float*>(
-                        tr.slot + 16 + rect_bytes + align16(sizeof(float) * (size_t)tr.alloc_rows * (P + 1)));
+            const int cb = b / kWave;
+            for (int rb = 0; rb < nrb; ++rb) {
+                const TileRef tr = tile_at(rb * ncb + cb);
+                const float* fv = reinterpret_cast<const float*>(
+                    tr.slot + 16 + rect_bytes + align16(sizeof(float) * (size_t)tr.alloc_rows * (P + 1)));
 #pragma unroll
-                    for (int h = 0; h <= Q; ++h) f[h] += (double)fv[(b - tr.col0) * (Q + 1) + h];
-                }
+                for (int h = 0; h <= Q; ++h) f[h] += (double)fv[(b - tr.col0) * (Q + 1) + h];
             }
         };
         knot_gradient<Q>(s.kv, s.nv_c, s.vs, s.nv_s, coef, gkv, L);
