@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -123,6 +125,77 @@ def parity_sample(batch, pts, grads, n: int = 12, seed: int = 23):
     return {"surfaces": len(idx), "max_point_err_rel_bbox": worst_p, "max_grad_err_rel_inf": worst_g}
 
 
+def served_leg(batch, n_req: int, seed: int = 4):
+    """Continuous-batching server on the batch's surfaces (resident): closed-
+    loop saturation, then Poisson arrivals at 0.5x, 0.8x and 1.0x of it, and
+    the per-request plain-launch baseline at the same rates (fewer requests:
+    it saturates far earlier)."""
+    from paper_2104_14547_amd.serve import PlainServer, Server, make_requests, run_load
+    reqs = make_requests(batch, n_req, seed=seed)
+    out = {"requests_per_rate": n_req, "rates": []}
+    with Server(batch, slot_bytes=1 << 30, n_slots=3, max_requests=512) as srv:
+        run_load(srv, reqs[: min(200, n_req)], rate=None)  # warm-up
+        sat, _ = run_load(srv, reqs, rate=None)
+        out["saturation_req_s"] = sat["req_per_s"]
+        out["saturation_pts_s"] = sat["pts_per_s"]
+        for f in (0.5, 0.8, 1.0):
+            st, _ = run_load(srv, reqs, rate=f * sat["req_per_s"], seed=seed + 1)
+            st["load"] = f
+            out["rates"].append(st)
+        out["batches"] = srv.batches
+    n_plain = min(n_req, 400)
+    plain = {"requests_per_rate": n_plain, "rates": []}
+    with PlainServer(batch) as ps:
+        run_load(ps, reqs[:20], rate=None)
+        st, _ = run_load(ps, reqs[:n_plain], rate=None)
+        plain["saturation_req_s"] = st["req_per_s"]
+        for f in (0.5, 0.8, 1.0):
+            st, _ = run_load(ps, reqs[:n_plain], rate=f * out["saturation_req_s"], seed=seed + 1)
+            st["load"] = f
+            plain["rates"].append(st)
+    out["plain_baseline"] = plain
+    return out
+
+
+def fit_leg(steps: int):
+    """The fitting loop (64x64 bicubic net, 512x512 samples of
+    z = sin 3x cos 3y, Adam lr 1e-2 on points, weights and knots), one HIP
+    graph launch per step."""
+    import torch
+    from paper_2104_14547_amd import workloads as W
+    from paper_2104_14547_amd.fit import SurfaceFit
+    b = W.fit_target(2)
+    d = b.surface(0)
+    dev = torch.device("cuda", 0)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    f = SurfaceFit(T(d["ctrl"]), T(d["w"]), T(d["ku"]), T(d["kv"]), d["p"], d["q"], T(d["us"]), T(d["vs"]),
+                   T(d["target"]), lr=1e-2, train_knots=True, graph=True)
+    l0 = f.loss()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": b.name, "steps": steps, "step_ms": dt / steps * 1e3,
+            "pts_per_s": b.n_points * steps / dt, "loss_start": l0, "loss_end": f.loss(),
+            "note": "whole step (fwd, dL/dS, bwd, Adam, projections) replayed as one HIP graph"}
+
+
+def copy_calibration(torch, dev, mib: int, reps: int = 3):
+    """A plain copy of known size: each launch reads and writes exactly
+    mib MiB, so what the FETCH_SIZE / WRITE_SIZE counters report for it gives
+    the factor that turns those counters into HBM bytes.  An elementwise
+    kernel (x * 1) rather than copy_, which may go to a DMA engine."""
+    n = mib * 2**20 // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": n * 4, "launches": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +205,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4096, help="surfaces timed on the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=3000,
+                    help="requests per arrival rate in the served leg (0: skip it)")
+    ap.add_argument("--fit-steps", type=int, default=500, help="steps of the fitting leg (0: skip it)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (scale for HBM byte counters) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -148,6 +226,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        copy_calibration(torch, dev, args.copy_calibration)
+        return
     t0 = time.perf_counter()
     if args.workload == "uneven_batch":
         batch = W.uneven_batch(3)
@@ -225,6 +306,14 @@ def main():
         t1 = time.perf_counter()
         result["parity"] = parity_sample(batch, pts.cpu().numpy(), [g.cpu().numpy() for g in grads])
         log(f"[bench] parity {result['parity']} ({time.perf_counter() - t1:.1f} s)")
+    if args.fit_steps > 0:
+        t1 = time.perf_counter()
+        result["fit"] = fit_leg(args.fit_steps)
+        log(f"[bench] fit {result['fit']} ({time.perf_counter() - t1:.1f} s)")
+    if args.served_requests > 0:
+        t1 = time.perf_counter()
+        result["served"] = served_leg(batch, args.served_requests)
+        log(f"[bench] served {result['served']} ({time.perf_counter() - t1:.1f} s)")
     if not args.no_cpu_baseline:
         t1 = time.perf_counter()
         result["cpu_baseline"] = cpu_baseline(batch, args.cpu_sample)

@@ -157,11 +157,29 @@ int nurbs_surface_bwd(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
  * The plan is bound to the device current at creation.  nurbs_plan_fwd /
  * nurbs_plan_bwd take packed arrays laid out as the descriptors say, launch
  * without host synchronisation or allocation, and may be captured in a HIP
- * graph.  Two calls of one plan must not run concurrently (they share the
- * plan's work counters); use one plan per stream.
+ * graph.  Tiles are assigned to the persistent waves when the plan is built
+ * (no device-side work queue), so calls of one plan on different streams may
+ * overlap as long as each has its own workspace and outputs; the host-side
+ * calls themselves are not thread-safe (one thread per plan).
  * ---------------------------------------------------------------------- */
 int nurbs_plan_create(nurbs_ctx *ctx, const nurbs_desc *host, int n, unsigned flags,
                       nurbs_plan **out, size_t *ws_bytes);
+/* The same plan with its device tables in caller memory, for loops that must
+ * neither allocate nor synchronise (a serving loop building one plan per
+ * batch of requests).
+ *   tables, tables_bytes : device memory for the tables (at least
+ *                 *table_bytes_needed bytes, 256-byte aligned).  NULL: size
+ *                 query only; table_bytes_needed and ws_bytes are filled and
+ *                 no plan is created (out may be NULL).
+ *   stream      : the tables are uploaded with an asynchronous copy on this
+ *                 stream; use the plan on it (or after it).
+ * The plan does not own `tables`; nurbs_plan_destroy frees only host state.
+ * Destroy the plan, and reuse `tables`, only after the stream has passed the
+ * plan's last launch.  Errors as nurbs_plan_create, and NURBS_EWORKSPACE when
+ * tables_bytes is too small. */
+int nurbs_plan_create_in(nurbs_ctx *ctx, const nurbs_desc *host, int n, unsigned flags,
+                         void *tables, size_t tables_bytes, void *stream,
+                         nurbs_plan **out, size_t *table_bytes_needed, size_t *ws_bytes);
 int nurbs_plan_destroy(nurbs_plan *plan);
 /* Tile statistics of a plan: number of forward / backward tiles. */
 int nurbs_plan_info(nurbs_plan *plan, int *fwd_tiles, int *bwd_tiles, int *grid);

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,7 @@ struct nurbs_ctx {
     int device = 0;
     unsigned flags = 0;
     int num_cus = 0;
+    int occ[2][2] = {{0, 0}, {0, 0}};  // persistent-kernel workgroups per CU: [class d5, d7][fwd, bwd]
     std::string err;
 };
 
@@ -33,19 +35,26 @@ struct nurbs_plan {
     void* dev = nullptr;
     DevDesc* d_desc = nullptr;
     DevTile* d_ftiles = nullptr;
-    int* d_forder = nullptr;
+    ExecTile* d_fexec = nullptr;  // forward execution records, wave order
     DevTile* d_btiles = nullptr;
-    int* d_border = nullptr;
-    unsigned* d_counters = nullptr;  // fwd pair, bwd pair
+    ExecTile* d_bexec = nullptr;  // backward execution records, wave order
+    int* d_fbegin = nullptr;      // wave boundaries in d_fexec
+    int* d_bbegin = nullptr;      // wave boundaries in d_bexec
     int nf = 0, nb = 0;
     int grid_fwd = 0, grid_bwd = 0;
     size_t ws_bytes = 0;
     int max_nU = 0, max_nV = 0;
     int maxd = 5;  // degree class of the persistent kernels (5 or 7)
+    std::vector<char> staging;  // host copy of the tables (plans made in caller memory)
     // tracing: event ring per direction (2 events per forward, 3 per backward)
     int trace_slots = 0;
     std::vector<hipEvent_t> ev_f, ev_b;
     long long calls_f = 0, calls_b = 0;
+};
+
+// byte offsets of the device tables inside one allocation
+struct PlanLayout {
+    size_t desc, ftiles, fexec, btiles, bexec, fbegin, bbegin, total;
 };
 
 namespace {
@@ -267,11 +276,11 @@ int nurbs_surface_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, c
         // no samples: every gradient is zero
         const size_t cp = (size_t)B * nu_c * nv_c;
         hipError_t e = hipSuccess;
-        if (grad_mask & NURBS_GRAD_CTRL) e = hipMemsetAsync(grad_ctrl, 0, cp * 3 * 4, st);
-        if (!e && (grad_mask & NURBS_GRAD_W)) e = hipMemsetAsync(grad_w, 0, cp * 4, st);
-        if (!e && (grad_mask & NURBS_GRAD_KU)) e = hipMemsetAsync(grad_ku, 0, (size_t)B * (nu_c + p + 1) * 4, st);
-        if (!e && (grad_mask & NURBS_GRAD_KV)) e = hipMemsetAsync(grad_kv, 0, (size_t)B * (nv_c + q + 1) * 4, st);
-        return e ? hip_fail(ctx, e, "hipMemsetAsync") : NURBS_OK;
+        if (grad_mask & NURBS_GRAD_CTRL) e = launch_zero(st, grad_ctrl, cp * 3);
+        if (!e && (grad_mask & NURBS_GRAD_W)) e = launch_zero(st, grad_w, cp);
+        if (!e && (grad_mask & NURBS_GRAD_KU)) e = launch_zero(st, grad_ku, (size_t)B * (nu_c + p + 1));
+        if (!e && (grad_mask & NURBS_GRAD_KV)) e = launch_zero(st, grad_kv, (size_t)B * (nv_c + q + 1));
+        return e ? hip_fail(ctx, e, "zero fill") : NURBS_OK;
     }
     if (!grad_pts) return fail(ctx, NURBS_EINVAL, "NULL grad_pts");
     const UniformGeom g = uniform_geom(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
@@ -287,7 +296,8 @@ int nurbs_surface_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, c
     case P:                                                                                               \
         e = launch_uniform_bwd_p##P(q, grid, st, a, grad_pts, slots, g.slot, grad_mask);                  \
         if (e == hipSuccess)                                                                              \
-            e = launch_uniform_fin_p##P(q, dim3(B), st, a, slots, g.slot, grad_ctrl, grad_w, grad_ku,      \
+            e = launch_uniform_fin_p##P(q, dim3((B + kWavesPerWG - 1) / kWavesPerWG), st, a, slots, g.slot,  \
+                                        grad_ctrl, grad_w, grad_ku,                                       \
                                         grad_kv, grad_mask);                                              \
         break;
         ND_CASE(1) ND_CASE(2) ND_CASE(3) ND_CASE(4) ND_CASE(5) ND_CASE(6) ND_CASE(7)
@@ -302,19 +312,50 @@ int nurbs_surface_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, c
 // --------------------------------------------------------------------------
 namespace {
 
-// relative cost of a tile (per-point work grows with the degree in u)
+// Estimated wave time of a tile (arbitrary units, about a microsecond): a
+// fixed set-up (dependent loads of the tile's tables, knots and first
+// control rows), a per-row cost growing with the degree in u and, in the
+// backward, a per-control-row flush growing with the degree in v.
 double tile_cost(const nurbs_desc& d, int rows, bool bwd) {
-    const double cols = std::min(kWave, d.nv_s);
-    const double pts = rows * cols;
-    const double per_pt = bwd ? (12.0 * (d.p + 1) + 16.0) : (4.0 * (d.p + 1) + 12.0);
-    const double setup = bwd ? (double)(d.nu_c) * 40.0 * (d.q + 1) : 8.0 * (d.p + 1) * (d.q + 1);
-    return pts * per_pt + setup;
+    if (!bwd) return 9.0 + rows * (0.40 + 0.06 * (d.p + 1));
+    const double crow = std::min<double>(d.nu_c, d.p + 1 + (double)rows * (d.nu_c - d.p) / std::max(d.nu_s, 1));
+    return 12.0 + rows * (1.0 + 0.25 * (d.p + 1)) + crow * (0.5 + 0.35 * (d.q + 1));
+}
+
+// Assign tiles to nw waves: longest first, each to the wave with the least
+// work so far.  Returns the tiles in wave order and the wave boundaries.
+void assign_waves(const std::vector<double>& cost, int nw, std::vector<int>& order, std::vector<int>& begin) {
+    std::vector<int> idx(cost.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    using Load = std::pair<double, int>;
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (int w = 0; w < nw; ++w) heap.push({0.0, w});
+    std::vector<std::vector<int>> lists(nw);
+    for (int t : idx) {
+        Load l = heap.top();
+        heap.pop();
+        lists[l.second].push_back(t);
+        l.first += cost[t];
+        heap.push(l);
+    }
+    order.clear();
+    begin.assign(nw + 1, 0);
+    for (int w = 0; w < nw; ++w) {
+        begin[w] = (int)order.size();
+        order.insert(order.end(), lists[w].begin(), lists[w].end());
+    }
+    begin[nw] = (int)order.size();
 }
 
 }  // namespace
 
-int nurbs_plan_create(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nurbs_plan** out,
-                      size_t* ws_bytes) {
+namespace {
+// Host half of plan creation: validate the descriptors, cut tiles, assign
+// them to waves and lay out the device tables in *blob.  The device pointers
+// are bound by plan_bind once the blob has a device address.
+int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nurbs_plan** out,
+               std::vector<char>* blob, PlanLayout* lay) {
     if (!ctx) return fail(nullptr, NURBS_EINVAL, "ctx is NULL");
     if (!out || (!host && n > 0) || n < 0) return fail(ctx, NURBS_EINVAL, "bad arguments");
     if (flags & ~NURBS_VALIDATE) return fail(ctx, NURBS_EINVAL, "unknown flag bits");
@@ -376,12 +417,6 @@ int nurbs_plan_create(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned fl
         pl->max_nU = std::max(pl->max_nU, d.nu_c + d.p + 1);
         pl->max_nV = std::max(pl->max_nV, d.nv_c + d.q + 1);
     }
-    // execution order: most expensive first (greedy longest-processing-time)
-    std::vector<int> fo(ft.size()), bo(bt.size());
-    std::iota(fo.begin(), fo.end(), 0);
-    std::iota(bo.begin(), bo.end(), 0);
-    std::stable_sort(fo.begin(), fo.end(), [&](int a, int b) { return fcost[a] > fcost[b]; });
-    std::stable_sort(bo.begin(), bo.end(), [&](int a, int b) { return bcost[a] > bcost[b]; });
     pl->nf = (int)ft.size();
     pl->nb = (int)bt.size();
     pl->ws_bytes = kWsHeader + slot_off;
@@ -390,51 +425,131 @@ int nurbs_plan_create(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned fl
     int maxdeg = 1;
     for (const auto& d : pl->host) maxdeg = std::max(maxdeg, std::max(d.p, d.q));
     pl->maxd = maxdeg <= 5 ? 5 : 7;
-    int occ_f = 0, occ_b = 0;
-    hipError_t e = pl->maxd == 5 ? occupancy_plan_fwd_d5(&occ_f) : occupancy_plan_fwd_d7(&occ_f);
-    if (e == hipSuccess) e = pl->maxd == 5 ? occupancy_plan_bwd_d5(&occ_b) : occupancy_plan_bwd_d7(&occ_b);
-    if (e != hipSuccess) {
-        delete pl;
-        return hip_fail(ctx, e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    int* occ = ctx->occ[pl->maxd == 5 ? 0 : 1];
+    if (occ[0] == 0 || occ[1] == 0) {  // asked once per context
+        hipError_t e = pl->maxd == 5 ? occupancy_plan_fwd_d5(&occ[0]) : occupancy_plan_fwd_d7(&occ[0]);
+        if (e == hipSuccess) e = pl->maxd == 5 ? occupancy_plan_bwd_d5(&occ[1]) : occupancy_plan_bwd_d7(&occ[1]);
+        if (e != hipSuccess) {
+            occ[0] = occ[1] = 0;
+            delete pl;
+            return hip_fail(ctx, e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+        }
     }
+    const int occ_f = std::max(occ[0], 1), occ_b = std::max(occ[1], 1);
     pl->grid_fwd = std::max(1, std::min(occ_f * cus, (pl->nf + kWavesPerWG - 1) / kWavesPerWG));
     pl->grid_bwd = std::max(1, std::min(occ_b * cus, (pl->nb + kWavesPerWG - 1) / kWavesPerWG));
+    std::vector<int> fo, fbeg, bo, bbeg;
+    assign_waves(fcost, pl->grid_fwd * kWavesPerWG, fo, fbeg);
+    assign_waves(bcost, pl->grid_bwd * kWavesPerWG, bo, bbeg);
+    auto record = [&](const DevTile& t) {
+        const DevDesc& x = dd[t.surf];
+        ExecTile r;
+        r.p = x.p; r.q = x.q; r.nu_c = x.nu_c; r.nv_c = x.nv_c; r.nu_s = x.nu_s; r.nv_s = x.nv_s;
+        r.col0 = t.col0; r.row0 = t.row0; r.row1 = t.row1; r.rows = x.rows;
+        r.ctrl_off = x.ctrl_off; r.w_off = x.w_off; r.ku_off = x.ku_off; r.kv_off = x.kv_off;
+        r.us_off = x.us_off; r.vs_off = x.vs_off; r.pts_off = x.pts_off; r.slot_off = t.slot_off;
+        return r;
+    };
+    std::vector<ExecTile> fx, bx;
+    for (int i : fo) fx.push_back(record(ft[i]));
+    for (int i : bo) bx.push_back(record(bt[i]));
 
     // upload tables
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     const size_t o_desc = 0;
     const size_t o_ft = o_desc + al(sizeof(DevDesc) * std::max(n, 1));
-    const size_t o_fo = o_ft + al(sizeof(DevTile) * std::max<size_t>(ft.size(), 1));
-    const size_t o_bt = o_fo + al(sizeof(int) * std::max<size_t>(fo.size(), 1));
-    const size_t o_bo = o_bt + al(sizeof(DevTile) * std::max<size_t>(bt.size(), 1));
-    const size_t o_ct = o_bo + al(sizeof(int) * std::max<size_t>(bo.size(), 1));
-    const size_t total = o_ct + 256;
-    std::vector<char> blob(total, 0);
-    if (n) memcpy(blob.data() + o_desc, dd.data(), sizeof(DevDesc) * n);
-    if (!ft.empty()) memcpy(blob.data() + o_ft, ft.data(), sizeof(DevTile) * ft.size());
-    if (!fo.empty()) memcpy(blob.data() + o_fo, fo.data(), sizeof(int) * fo.size());
-    if (!bt.empty()) memcpy(blob.data() + o_bt, bt.data(), sizeof(DevTile) * bt.size());
-    if (!bo.empty()) memcpy(blob.data() + o_bo, bo.data(), sizeof(int) * bo.size());
-    e = hipMalloc(&pl->dev, total);
+    const size_t o_fx = o_ft + al(sizeof(DevTile) * std::max<size_t>(ft.size(), 1));
+    const size_t o_bt = o_fx + al(sizeof(ExecTile) * std::max<size_t>(fx.size(), 1));
+    const size_t o_bx = o_bt + al(sizeof(DevTile) * std::max<size_t>(bt.size(), 1));
+    const size_t o_fb = o_bx + al(sizeof(ExecTile) * std::max<size_t>(bx.size(), 1));
+    const size_t o_bb = o_fb + al(sizeof(int) * fbeg.size());
+    const size_t total = o_bb + al(sizeof(int) * bbeg.size());
+    blob->assign(total, 0);
+    char* hb = blob->data();
+    if (n) memcpy(hb + o_desc, dd.data(), sizeof(DevDesc) * n);
+    if (!ft.empty()) memcpy(hb + o_ft, ft.data(), sizeof(DevTile) * ft.size());
+    if (!fx.empty()) memcpy(hb + o_fx, fx.data(), sizeof(ExecTile) * fx.size());
+    if (!bt.empty()) memcpy(hb + o_bt, bt.data(), sizeof(DevTile) * bt.size());
+    if (!bx.empty()) memcpy(hb + o_bx, bx.data(), sizeof(ExecTile) * bx.size());
+    memcpy(hb + o_fb, fbeg.data(), sizeof(int) * fbeg.size());
+    memcpy(hb + o_bb, bbeg.data(), sizeof(int) * bbeg.size());
+    *lay = PlanLayout{o_desc, o_ft, o_fx, o_bt, o_bx, o_fb, o_bb, total};
+    *out = pl;
+    return NURBS_OK;
+}
+
+void plan_bind(nurbs_plan* pl, void* dev, const PlanLayout& lay) {
+    char* base = reinterpret_cast<char*>(dev);
+    pl->d_desc = reinterpret_cast<DevDesc*>(base + lay.desc);
+    pl->d_ftiles = reinterpret_cast<DevTile*>(base + lay.ftiles);
+    pl->d_fexec = reinterpret_cast<ExecTile*>(base + lay.fexec);
+    pl->d_btiles = reinterpret_cast<DevTile*>(base + lay.btiles);
+    pl->d_bexec = reinterpret_cast<ExecTile*>(base + lay.bexec);
+    pl->d_fbegin = reinterpret_cast<int*>(base + lay.fbegin);
+    pl->d_bbegin = reinterpret_cast<int*>(base + lay.bbegin);
+}
+}  // namespace
+
+int nurbs_plan_create(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nurbs_plan** out,
+                      size_t* ws_bytes) {
+    std::vector<char> blob;
+    PlanLayout lay;
+    nurbs_plan* pl = nullptr;
+    int rc = plan_build(ctx, host, n, flags, &pl, &blob, &lay);
+    if (rc) return rc;
+    hipError_t e = hipMalloc(&pl->dev, lay.total);
     if (e != hipSuccess) {
         delete pl;
         return hip_fail(ctx, e, "hipMalloc(plan tables)");
     }
-    e = hipMemcpy(pl->dev, blob.data(), total, hipMemcpyHostToDevice);
+    e = hipMemcpy(pl->dev, blob.data(), lay.total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(pl->dev);
         delete pl;
         return hip_fail(ctx, e, "hipMemcpy(plan tables)");
     }
-    char* base = reinterpret_cast<char*>(pl->dev);
-    pl->d_desc = reinterpret_cast<DevDesc*>(base + o_desc);
-    pl->d_ftiles = reinterpret_cast<DevTile*>(base + o_ft);
-    pl->d_forder = reinterpret_cast<int*>(base + o_fo);
-    pl->d_btiles = reinterpret_cast<DevTile*>(base + o_bt);
-    pl->d_border = reinterpret_cast<int*>(base + o_bo);
-    pl->d_counters = reinterpret_cast<unsigned*>(base + o_ct);
+    plan_bind(pl, pl->dev, lay);
     *out = pl;
     if (ws_bytes) *ws_bytes = pl->ws_bytes;
+    return NURBS_OK;
+}
+
+int nurbs_plan_create_in(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, void* tables,
+                         size_t tables_bytes, void* stream, nurbs_plan** out, size_t* table_bytes_needed,
+                         size_t* ws_bytes) {
+    std::vector<char> blob;
+    PlanLayout lay;
+    nurbs_plan* pl = nullptr;
+    if (out) *out = nullptr;
+    nurbs_plan* tmp = nullptr;
+    int rc = plan_build(ctx, host, n, flags, &tmp, &blob, &lay);
+    if (rc) return rc;
+    pl = tmp;
+    if (table_bytes_needed) *table_bytes_needed = lay.total;
+    if (ws_bytes) *ws_bytes = pl->ws_bytes;
+    if (!tables) {  // size query
+        delete pl;
+        return NURBS_OK;
+    }
+    if (!out) {
+        delete pl;
+        return fail(ctx, NURBS_EINVAL, "out is NULL");
+    }
+    if (tables_bytes < lay.total) {
+        delete pl;
+        return fail(ctx, NURBS_EWORKSPACE, "table memory too small: need " + std::to_string(lay.total));
+    }
+    // the blob stays with the plan until it is destroyed, so the asynchronous
+    // copy never reads freed host memory
+    pl->staging = std::move(blob);
+    hipError_t e = hipMemcpyAsync(tables, pl->staging.data(), lay.total, hipMemcpyHostToDevice,
+                                  reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        delete pl;
+        return hip_fail(ctx, e, "hipMemcpyAsync(plan tables)");
+    }
+    plan_bind(pl, tables, lay);
+    *out = pl;
     return NURBS_OK;
 }
 
@@ -460,13 +575,14 @@ PlanArgs plan_args(nurbs_plan* pl, bool bwd, void* ws, const float* ctrl, const 
     PlanArgs a;
     a.desc = pl->d_desc;
     a.tiles = bwd ? pl->d_btiles : pl->d_ftiles;
-    a.order = bwd ? pl->d_border : pl->d_forder;
+    a.exec = bwd ? pl->d_bexec : pl->d_fexec;
     a.ntiles = bwd ? pl->nb : pl->nf;
-    a.counter = pl->d_counters + (bwd ? 2 : 0);
+    a.wave_begin = bwd ? pl->d_bbegin : pl->d_fbegin;
     a.nwaves = (bwd ? pl->grid_bwd : pl->grid_fwd) * kWavesPerWG;
     a.flags = pl->flags;
     a.err = (pl->flags & NURBS_VALIDATE) ? reinterpret_cast<int*>(ws) : nullptr;
     a.ctrl = ctrl; a.w = w; a.ku = ku; a.kv = kv; a.us = us; a.vs = vs;
+    a.nsurf = pl->n;
     return a;
 }
 }  // namespace
@@ -521,8 +637,10 @@ int nurbs_plan_bwd(nurbs_plan* pl, const float* ctrl, const float* w, const floa
     if (ev && e == hipSuccess) e = hipEventRecord(ev[1], st);
     if (e == hipSuccess)
         e = pl->maxd == 5
-                ? launch_plan_fin_d5(dim3(pl->n), st, a, slots, grad_ctrl, grad_w, grad_ku, grad_kv, grad_mask)
-                : launch_plan_fin_d7(dim3(pl->n), st, a, slots, grad_ctrl, grad_w, grad_ku, grad_kv, grad_mask);
+                ? launch_plan_fin_d5(dim3((pl->n + kWavesPerWG - 1) / kWavesPerWG), st, a, slots, grad_ctrl, grad_w,
+                                     grad_ku, grad_kv, grad_mask)
+                : launch_plan_fin_d7(dim3((pl->n + kWavesPerWG - 1) / kWavesPerWG), st, a, slots, grad_ctrl, grad_w,
+                                     grad_ku, grad_kv, grad_mask);
     if (ev && e == hipSuccess) e = hipEventRecord(ev[2], st);
     if (e != hipSuccess) return hip_fail(pl->ctx, e, "launch plan backward");
     return NURBS_OK;

@@ -3,9 +3,11 @@
 // Span search and basis (Sec. 3.1.2 steps 1-2 of NURBS-Diff, eqs. NURBSBasis
 // and BSplineBasis2), the homogeneous control point (Sec. 3.1.2 step 3), the
 // reverse-mode knot derivative of the recursion (Sec. 3.2.1) and wave-level
-// helpers.  Per-row / per-column set-up work (span, basis, knot derivatives)
-// runs in FP64: it is O(nu_s + nv_s) per surface, so its cost is not
-// measurable next to the O(nu_s * nv_s) per-point work, which runs in FP32.
+// helpers.  Everything runs in FP32 on FP32 inputs: span search compares the
+// input values exactly; every factor of the basis recursion and of its knot
+// derivative is a ratio of differences of input values, so each carries a
+// few ulp of relative error.  Only the per-knot sums of the knot gradient
+// (long sums over samples) accumulate in FP64.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -19,6 +21,16 @@ constexpr int kMaxDeg = 7;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// The lane index as a value the compiler cannot see through.  Rare-path code
+// (block staging, flushes) derives its addresses from it, so those addresses
+// are recomputed where they are used instead of being hoisted out of the row
+// loops and held in registers for the whole tile.
+__device__ __forceinline__ int lane_opaque() {
+    int l = __lane_id();
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
 __device__ __forceinline__ int bcast_lane(int x, int l) {
     return __builtin_amdgcn_readlane(x, l);
 }
@@ -31,6 +43,14 @@ __device__ __forceinline__ long long uniform64(long long x) {
     const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)x >> 32));
     return (long long)(((unsigned long long)hi << 32) | lo);
 }
+
+// Wait until every global memory operation this wave issued has completed
+// (s_waitcnt vmcnt(0); gfx9 encoding, expcnt and lgkmcnt left at their
+// maxima).  Placed at the end of a conditional staging step, it tells the
+// compiler that nothing is outstanding on any path out of the step, so no
+// conservative vmcnt(0) -- which also waits for earlier stores -- is inserted
+// at later uses of the staging registers inside the hot loop.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // Order this wave's LDS traffic: everything before is visible to every lane
 // after (LDS executes in order per wave; this stops compiler reordering).
@@ -92,95 +112,74 @@ __device__ __forceinline__ int find_span(const float* __restrict__ U, int deg, i
     return lo;
 }
 
-// The D+1 non-zero basis functions N_{k-D..k}^D(x) on span k, by the
-// triangular Cox-de Boor scheme with left/right knot distances.  Every
-// denominator is a knot difference that contains [U_k, U_{k+1}], so it is
-// positive on a non-empty span.
-template <int D>
-__device__ __forceinline__ void basis_f64(const float* __restrict__ U, int k, float xf, double N[D + 1]) {
-    const double x = xf;
-    double left[D + 1], right[D + 1];
-    N[0] = 1.0;
-#pragma unroll
-    for (int j = 1; j <= D; ++j) {
-        left[j] = x - (double)U[k + 1 - j];
-        right[j] = (double)U[k + j] - x;
-        double saved = 0.0;
-#pragma unroll
-        for (int r = 0; r < j; ++r) {
-            const double tmp = N[r] / (right[r + 1] + left[j - r]);
-            N[r] = saved + right[r + 1] * tmp;
-            saved = left[j - r] * tmp;
-        }
-        N[j] = saved;
-    }
-}
-
 // Reverse-mode derivative of Phi = sum_r e[r] N_{k-D+r}^D(x) with respect to
 // the knots U_{k-D} .. U_{k+D+1} (gU[t] <-> U_{k-D+t}), through the
 // recursion N_i^d = alpha N_i^{d-1} + beta N_{i+1}^{d-1},
 // alpha = (x-U_i)/(U_{i+d}-U_i), beta = (U_{i+d+1}-x)/(U_{i+d+1}-U_{i+1}).
 // The degree-0 indicator contributes no knot derivative (zero-bandwidth
 // limit of the paper's smoothing), so only the alpha/beta factors do.
+// FP32: every factor is a ratio of FP32 knot differences, so the result is
+// accurate to a few ulp per term.
 template <int D>
-__device__ __forceinline__ void basis_knot_adjoint(const float* __restrict__ U, int k, float xf,
-                                                   const double e[D + 1], double gU[2 * D + 2]) {
-    const double x = xf;
+__device__ __forceinline__ void basis_knot_adjoint(const float* __restrict__ U, int k, float x,
+                                                   const float e[D + 1], float gU[2 * D + 2]) {
     // forward triangle T[d][idx] = N_{k-d+idx}^d
-    double T[D + 1][D + 1];
-    T[0][0] = 1.0;
+    float T[D + 1][D + 1];
+    T[0][0] = 1.0f;
 #pragma unroll
     for (int d = 1; d <= D; ++d) {
 #pragma unroll
         for (int idx = 0; idx <= d; ++idx) {
             const int i = k - d + idx;
-            double v = 0.0;
+            float v = 0.0f;
             if (idx >= 1) {
-                const double den = (double)U[i + d] - (double)U[i];
-                if (den != 0.0) v += (x - (double)U[i]) / den * T[d - 1][idx - 1];
+                const float den = U[i + d] - U[i];
+                if (den != 0.0f) v += (x - U[i]) / den * T[d - 1][idx - 1];
             }
             if (idx <= d - 1) {
-                const double den = (double)U[i + d + 1] - (double)U[i + 1];
-                if (den != 0.0) v += ((double)U[i + d + 1] - x) / den * T[d - 1][idx];
+                const float den = U[i + d + 1] - U[i + 1];
+                if (den != 0.0f) v += (U[i + d + 1] - x) / den * T[d - 1][idx];
             }
             T[d][idx] = v;
         }
     }
 #pragma unroll
-    for (int t = 0; t < 2 * D + 2; ++t) gU[t] = 0.0;
-    double A[D + 1];
+    for (int t = 0; t < 2 * D + 2; ++t) gU[t] = 0.0f;
+    float A[D + 1];
 #pragma unroll
     for (int r = 0; r <= D; ++r) A[r] = e[r];
 #pragma unroll
     for (int d = D; d >= 1; --d) {
-        double An[D + 1];
+        float An[D + 1];
 #pragma unroll
-        for (int r = 0; r <= D; ++r) An[r] = 0.0;
+        for (int r = 0; r <= D; ++r) An[r] = 0.0f;
 #pragma unroll
         for (int idx = 0; idx <= d; ++idx) {
             const int i = k - d + idx;
             const int t = D - d + idx;  // window slot of U_i
-            const double Ai = A[idx];
+            const float Ai = A[idx];
             if (idx >= 1) {
-                const double Ui = U[i], Uid = U[i + d];
-                const double den = Uid - Ui;
-                if (den != 0.0) {
-                    const double Np = T[d - 1][idx - 1];
-                    const double inv2 = 1.0 / (den * den);
-                    An[idx - 1] += Ai * (x - Ui) / den;
-                    gU[t] += Ai * Np * (x - Uid) * inv2;
-                    gU[t + d] -= Ai * Np * (x - Ui) * inv2;
+                const float Ui = U[i], Uid = U[i + d];
+                const float den = Uid - Ui;
+                if (den != 0.0f) {
+                    const float Np = T[d - 1][idx - 1];
+                    const float inv = 1.0f / den;
+                    const float c = Ai * Np * inv * inv;
+                    An[idx - 1] += Ai * (x - Ui) * inv;
+                    gU[t] += c * (x - Uid);
+                    gU[t + d] -= c * (x - Ui);
                 }
             }
             if (idx <= d - 1) {
-                const double Ui1 = U[i + 1], Uid1 = U[i + d + 1];
-                const double den = Uid1 - Ui1;
-                if (den != 0.0) {
-                    const double Np = T[d - 1][idx];
-                    const double inv2 = 1.0 / (den * den);
-                    An[idx] += Ai * (Uid1 - x) / den;
-                    gU[t + 1] += Ai * Np * (Uid1 - x) * inv2;
-                    gU[t + d + 1] += Ai * Np * (x - Ui1) * inv2;
+                const float Ui1 = U[i + 1], Uid1 = U[i + d + 1];
+                const float den = Uid1 - Ui1;
+                if (den != 0.0f) {
+                    const float Np = T[d - 1][idx];
+                    const float inv = 1.0f / den;
+                    const float c = Ai * Np * inv * inv;
+                    An[idx] += Ai * (Uid1 - x) * inv;
+                    gU[t + 1] += c * (Uid1 - x);
+                    gU[t + d + 1] += c * (x - Ui1);
                 }
             }
         }
@@ -229,16 +228,37 @@ __device__ __forceinline__ float4 row_contract(const Surf& s, int i, int jb, con
     return acc;
 }
 
+// The D+1 non-zero basis functions N_{k-D..k}^D(x) on span k, by the
+// triangular Cox-de Boor scheme with left/right knot distances.  Every
+// denominator is a knot difference that contains [U_k, U_{k+1}], so it is
+// positive on a non-empty span.  FP32: the differences of FP32 inputs carry
+// one rounding each, so the values are accurate to a few ulp per degree.
+template <int D>
+__device__ __forceinline__ void basis_f32(const float* __restrict__ U, int k, float x, float N[D + 1]) {
+    float left[D + 1], right[D + 1];
+    N[0] = 1.0f;
+#pragma unroll
+    for (int j = 1; j <= D; ++j) {
+        left[j] = x - U[k + 1 - j];
+        right[j] = U[k + j] - x;
+        float saved = 0.0f;
+#pragma unroll
+        for (int r = 0; r < j; ++r) {
+            const float tmp = N[r] / (right[r + 1] + left[j - r]);
+            N[r] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        N[j] = saved;
+    }
+}
+
 // Span and FP32 basis of one sample along a direction with degree D.
 template <int D>
 __device__ __forceinline__ int sample_basis(const float* __restrict__ U, int nc, float x, float N[D + 1]) {
     const int n = nc - 1;
     const float xc = clamp_param(U, D, n, x);
     const int k = find_span(U, D, n, xc);
-    double Nd[D + 1];
-    basis_f64<D>(U, k, xc, Nd);
-#pragma unroll
-    for (int r = 0; r <= D; ++r) N[r] = (float)Nd[r];
+    basis_f32<D>(U, k, xc, N);
     return k;
 }
 

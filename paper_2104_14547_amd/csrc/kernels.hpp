@@ -27,7 +27,7 @@
 // slots in a fixed order, so results are bitwise reproducible and do not
 // depend on which wave ran which tile.
 //
-// Finalize, one workgroup per surface: dL/dPw = sum of tile rectangles;
+// Finalize, one wave per surface: dL/dPw = sum of tile rectangles;
 // dL/dP = w dL/dPw_xyz, dL/dw = P . dL/dPw_xyz + dL/dPw_w; dL/dU_k by the
 // reverse-mode knot derivative of each row's basis weighted with e(a)
 // (Sec. 3.2.1), dL/dV_k likewise with f(b).
@@ -103,42 +103,94 @@ __device__ __forceinline__ void validate_surface(const Surf& s, int P, int Q, in
 }
 
 // --------------------------------------------------------------------------
-// control-row ring: the rows of the u-window (and the next one) for the
-// tile's control columns j0 .. j0+ncols-1, as homogeneous points in LDS
+// control-row block: consecutive control rows of the tile's control columns
+// j0 .. j0+ncols-1, as homogeneous points in LDS.  A block is loaded with all
+// its loads in flight at once (one memory latency) and replaced only when
+// the u-window leaves it, so the row loops below carry no pending loads.
 // --------------------------------------------------------------------------
-constexpr int kRingCap = 384;  // float4 entries per wave (6 KiB)
-constexpr int kEBatch = 16;    // rows per batched reduction of dL/dN(u)
+constexpr int kBlkCap = 384;                 // float4 entries per wave (6 KiB)
+constexpr int kBlkPerLane = kBlkCap / kWave;  // entries each lane loads
+constexpr int kEBatch = 16;                   // rows per batched reduction of dL/dN(u)
+constexpr int kGRows = 2;                     // rows of dL/dS staged per batch
 
-struct Ring {
-    float4* base;  // LDS, kRingCap entries
-    int j0, ncols, nslots;
-    bool on;       // false: the tile's column range does not fit, read Pw from global
+struct Block {
+    float4* base;  // LDS, [rows][ncols]
+    int j0, ncols;
+    int lo, hi;    // staged control rows [lo, hi]
+    int cap_rows;  // rows that fit
+    bool on;       // false: the column range is too wide, read control points from global
 };
 
-__device__ __forceinline__ float4* ring_row(const Ring& rg, int i) { return rg.base + (i % rg.nslots) * rg.ncols; }
-
-// Lanes load control row i (columns j0 .. j0+ncols-1) into registers; the
-// ring stores them later, so the load latency overlaps other work.
-struct RowPrefetch {
-    float4 v;  // column j0 + lane (the ring holds at most 64 columns)
-};
-
-__device__ __forceinline__ void prefetch_row(const Surf& s, const Ring& rg, int i, RowPrefetch& pf) {
-    const int lane = lane_id();
-    if (i < s.nu_c && lane < rg.ncols) pf.v = load_pw(s, i, rg.j0 + lane);
+__device__ __forceinline__ Block make_block(float4* base, int j0, int ncols, int p) {
+    Block bk;
+    bk.base = base;
+    bk.j0 = j0;
+    bk.ncols = ncols;
+    bk.lo = 0;
+    bk.hi = -1;
+    bk.cap_rows = kBlkCap / max(ncols, 1);
+    bk.on = bk.cap_rows >= p + 1;
+    return bk;
 }
 
-__device__ __forceinline__ void store_row(const Ring& rg, int i, const RowPrefetch& pf) {
-    const int lane = lane_id();
-    if (lane < rg.ncols) ring_row(rg, i)[lane] = pf.v;
+// Load control rows [lo, min(lo + cap_rows, nu_c) - 1] into the block.
+__device__ __forceinline__ void stage_block(const Surf& s, Block& bk, int lo) {
+    const int lane = lane_opaque();
+    bk.lo = lo;
+    bk.hi = min(lo + bk.cap_rows, s.nu_c) - 1;
+    const int n = (bk.hi - bk.lo + 1) * bk.ncols;
+    constexpr int kRound = kBlkPerLane / 2;  // loads in flight per lane per round
+#pragma unroll
+    for (int m0 = 0; m0 < kBlkPerLane; m0 += kRound) {
+        if (m0 * kWave >= n) break;
+        float4 raw[kRound];
+#pragma unroll
+        for (int m = 0; m < kRound; ++m) {
+            const int e = lane + (m0 + m) * kWave;
+            if (e < n) {
+                const int r = e / bk.ncols, c = e - r * bk.ncols;
+                const int ij = (lo + r) * s.nv_c + bk.j0 + c;
+                const float* cp = s.ctrl + 3 * ij;
+                raw[m] = make_float4(cp[0], cp[1], cp[2], s.w[ij]);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < kRound; ++m) {
+            const int e = lane + (m0 + m) * kWave;
+            if (e < n)
+                bk.base[e] = make_float4(raw[m].x * raw[m].w, raw[m].y * raw[m].w, raw[m].z * raw[m].w, raw[m].w);
+        }
+    }
+    wait_vmem();
+    wave_lds_sync();
 }
 
-// R_i(b) for this lane's column from the ring (or from global memory).
-template <int QM>
-__device__ __forceinline__ float4 ring_contract(const Surf& s, const Ring& rg, int i, int jb,
-                                                const float Nv[QM + 1], int q) {
-    if (!rg.on) return row_contract<QM>(s, i, jb, Nv, q);
-    const float4* row = ring_row(rg, i) + (jb - rg.j0);
+// Make sure rows [need_lo, need_hi] are staged (need_hi - need_lo < cap_rows).
+// The row loops are compiled twice, with BLK = bk.on known: the block
+// version has no global loads between restagings, so no wait on memory
+// (which on gfx9 also waits for this wave's earlier stores) sits in it.
+template <bool BLK>
+__device__ __forceinline__ void ensure_rows(const Surf& s, Block& bk, int need_lo, int need_hi) {
+    if constexpr (BLK) {
+        if (need_lo < bk.lo || need_hi > bk.hi) {
+            wave_lds_sync();
+            stage_block(s, bk, need_lo);
+        }
+    }
+}
+
+// Homogeneous control points of row i starting at this lane's first column
+// jb: a pointer into the block.
+__device__ __forceinline__ const float4* block_row(const Block& bk, int i, int jb) {
+    return bk.base + (i - bk.lo) * bk.ncols + (jb - bk.j0);
+}
+
+// R_i(b) for this lane's column from the block (or from global memory).
+template <int QM, bool BLK>
+__device__ __forceinline__ float4 blk_contract(const Surf& s, const Block& bk, int i, int jb,
+                                               const float Nv[QM + 1], int q) {
+    if constexpr (!BLK) return row_contract<QM>(s, i, jb, Nv, q);
+    const float4* row = block_row(bk, i, jb);
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int h = 0; h <= QM; ++h)
@@ -146,15 +198,49 @@ __device__ __forceinline__ float4 ring_contract(const Surf& s, const Ring& rg, i
     return acc;
 }
 
+// First inputs of a tile, fetched together (one memory latency): both knot
+// vectors (<= kWG entries each) into this wave's LDS, so that span searches
+// and basis evaluations read LDS; the lane's v parameter; and the u
+// parameter of the lane's row in the tile's first 64-row chunk.
+struct TileIn {
+    float v;   // vs[col0 + lane] (clamped to the last column)
+    float u0;  // us[row0 + lane] (clamped to the chunk)
+};
+
+__device__ __forceinline__ TileIn stage_tile(const Surf& sg, int p, int q, int col0, int row0, int row1,
+                                             float* ku_dst, float* kv_dst) {
+    const int lane = lane_id();
+    const int nU = sg.nu_c + p + 1, nV = sg.nv_c + q + 1;
+    float a[kWG / kWave], c[kWG / kWave];
+#pragma unroll
+    for (int m = 0; m < kWG / kWave; ++m) {
+        const int i = lane + m * kWave;
+        if (i < nU) a[m] = sg.ku[i];
+        if (i < nV) c[m] = sg.kv[i];
+    }
+    TileIn in;
+    in.v = sg.vs[min(col0 + lane, sg.nv_s - 1)];
+    in.u0 = sg.us[row0 + min(lane, min(kWave, row1 - row0) - 1)];
+#pragma unroll
+    for (int m = 0; m < kWG / kWave; ++m) {
+        const int i = lane + m * kWave;
+        if (i < nU) ku_dst[i] = a[m];
+        if (i < nV) kv_dst[i] = c[m];
+    }
+    wait_vmem();
+    wave_lds_sync();
+    return in;
+}
+
 // Column set-up shared by forward and backward: this lane's v-span and
 // basis, and the tile's control-column range [j0, j0 + ncols).
 template <int QM>
-__device__ __forceinline__ int tile_columns(const Surf& s, int q, int col0, float Nv[QM + 1], bool& act,
+__device__ __forceinline__ int tile_columns(const Surf& s, int q, int col0, float vb, float Nv[QM + 1], bool& act,
                                             int& j0, int& ncols) {
     const int lane = lane_id();
     const int b = col0 + lane;
     act = b < s.nv_s;
-    const int kb = sample_basis_rt<QM>(s.kv, s.nv_c, s.vs[act ? b : s.nv_s - 1], q, Nv);
+    const int kb = sample_basis_rt<QM>(s.kv, s.nv_c, vb, q, Nv);
     const int nact = min(kWave, s.nv_s - col0);
     const int kfirst = bcast_lane(kb, 0);
     const int klast = bcast_lane(kb, nact - 1);
@@ -163,58 +249,55 @@ __device__ __forceinline__ int tile_columns(const Surf& s, int q, int col0, floa
     return kb;
 }
 
-// Copy a knot vector (<= kWG entries) into this wave's LDS, so that span
-// searches and basis evaluations read LDS instead of chasing global loads.
-__device__ __forceinline__ const float* stage_knots(const float* __restrict__ U, int n, float* dst) {
-    const int lane = lane_id();
-    float v[kWG / kWave];
-#pragma unroll
-    for (int m = 0; m < kWG / kWave; ++m) {
-        const int i = lane + m * kWave;
-        if (i < n) v[m] = U[i];
-    }
-#pragma unroll
-    for (int m = 0; m < kWG / kWave; ++m) {
-        const int i = lane + m * kWave;
-        if (i < n) dst[i] = v[m];
-    }
-    return dst;
-}
-
-// The first P+2 ring rows (window rows k-P .. k and the next one), loads
-// issued together so the tile waits for one memory latency, not P+2.
-template <int P>
-__device__ __forceinline__ void stage_ring(const Surf& s, const Ring& rg, int k) {
-    const int lane = lane_id();
-    float4 v[P + 2];
-#pragma unroll
-    for (int r = 0; r < P + 2; ++r) {
-        const int i = k - P + r;
-        if (i < s.nu_c && lane < rg.ncols) v[r] = load_pw(s, i, rg.j0 + lane);
-    }
-#pragma unroll
-    for (int r = 0; r < P + 2; ++r)
-        if (lane < rg.ncols) ring_row(rg, k - P + r)[lane] = v[r];
-}
-
-__device__ __forceinline__ Ring make_ring(float4* base, int j0, int ncols, int p) {
-    Ring rg;
-    rg.base = base;
-    rg.j0 = j0;
-    rg.ncols = ncols;
-    rg.nslots = p + 2;
-    rg.on = ncols <= kWave && (p + 2) * ncols <= kRingCap;
-    return rg;
-}
-
 // --------------------------------------------------------------------------
 // forward tile
 // --------------------------------------------------------------------------
-// per-wave LDS of the forward tile
 struct FwdLds {
-    float4 ring[kRingCap];
+    float4 blk[kBlkCap];
     float knots[2][kWG];
 };
+
+template <int P, int QM, bool BLK>
+__device__ __forceinline__ void fwd_rows(const Surf& s, Block& bk, const float Nv[QM + 1], int q, int jb, bool act,
+                                         int row0, int row1, float u0, float* __restrict__ orow, size_t ostride) {
+    const int lane = lane_id();
+    float4 R[P + 1];
+    int cur = -1;  // window rows cur-P .. cur
+    for (int a0 = row0; a0 < row1; a0 += kWave) {
+        const int nr = min(kWave, row1 - a0);
+        float Nu_l[P + 1];
+        const float ua = a0 == row0 ? u0 : s.us[a0 + min(lane, nr - 1)];
+        const int ka_l = sample_basis<P>(s.ku, s.nu_c, ua, Nu_l);
+        for (int t = 0; t < nr; ++t) {
+            const int ka = bcast_lane(ka_l, t);
+            if (ka != cur) {
+                ensure_rows<BLK>(s, bk, ka - P, ka);
+                if (cur >= 0 && ka > cur && ka - cur <= P) {
+                    do {
+#pragma unroll
+                        for (int r = 0; r < P; ++r) R[r] = R[r + 1];
+                        ++cur;
+                        R[P] = blk_contract<QM, BLK>(s, bk, cur, jb, Nv, q);
+                    } while (cur < ka);
+                } else {
+                    cur = ka;
+#pragma unroll
+                    for (int r = 0; r <= P; ++r) R[r] = blk_contract<QM, BLK>(s, bk, ka - P + r, jb, Nv, q);
+                }
+            }
+            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int r = 0; r <= P; ++r) acc = fma4(bcast_lane(Nu_l[r], t), R[r], acc);
+            const float rw = recip(acc.w);
+            if (act) {
+                orow[0] = acc.x * rw;
+                orow[1] = acc.y * rw;
+                orow[2] = acc.z * rw;
+            }
+            orow += ostride;
+        }
+    }
+}
 
 template <int P, int QM>
 __device__ __forceinline__ void fwd_tile(const Surf& sg, int q, int col0, int row0, int row1,
@@ -223,67 +306,21 @@ __device__ __forceinline__ void fwd_tile(const Surf& sg, int q, int col0, int ro
     const int b = col0 + lane;
     // knots from LDS from here on
     Surf s = sg;
-    s.ku = stage_knots(sg.ku, sg.nu_c + P + 1, lds->knots[0]);
-    s.kv = stage_knots(sg.kv, sg.nv_c + q + 1, lds->knots[1]);
-    wave_lds_sync();
-    float4* ring_lds = lds->ring;
+    const TileIn in = stage_tile(sg, P, q, col0, row0, row1, lds->knots[0], lds->knots[1]);
+    s.ku = lds->knots[0];
+    s.kv = lds->knots[1];
     float Nv[QM + 1];
     bool act;
     int j0, ncols;
-    const int kb = tile_columns<QM>(s, q, col0, Nv, act, j0, ncols);
+    const int kb = tile_columns<QM>(s, q, col0, in.v, Nv, act, j0, ncols);
     const int jb = kb - q;
-    const Ring rg = make_ring(ring_lds, j0, ncols, P);
-
-    float4 R[P + 1];
-    RowPrefetch pf;
-    int cur = -1;  // window rows cur-P .. cur; ring holds rows up to nxt-1
-    int nxt = 0;
-    float u_next = s.us[min(row0 + lane, row1 - 1)];
-    for (int a0 = row0; a0 < row1; a0 += kWave) {
-        const int nr = min(kWave, row1 - a0);
-        float Nu_l[P + 1];
-        const int ka_l = sample_basis<P>(s.ku, s.nu_c, u_next, Nu_l);
-        if (a0 + kWave < row1) u_next = s.us[min(a0 + kWave + lane, row1 - 1)];
-        for (int t = 0; t < nr; ++t) {
-            const int ka = bcast_lane(ka_l, t);
-            if (cur < 0) {
-                // first row: stage rows ka-P .. ka+1, prefetch ka+2
-                if (rg.on) {
-                    stage_ring<P>(s, rg, ka);
-                    wave_lds_sync();
-                    nxt = ka + 2;
-                    prefetch_row(s, rg, nxt, pf);
-                }
-                cur = ka;
-#pragma unroll
-                for (int r = 0; r <= P; ++r) R[r] = ring_contract<QM>(s, rg, ka - P + r, jb, Nv, q);
-            } else {
-                while (cur < ka) {
-#pragma unroll
-                    for (int r = 0; r < P; ++r) R[r] = R[r + 1];
-                    ++cur;
-                    R[P] = ring_contract<QM>(s, rg, cur, jb, Nv, q);
-                    if (rg.on) {
-                        wave_lds_sync();
-                        store_row(rg, nxt, pf);  // replaces row cur-P-1, now outside the window
-                        wave_lds_sync();
-                        ++nxt;
-                        prefetch_row(s, rg, nxt, pf);
-                    }
-                }
-            }
-            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-            for (int r = 0; r <= P; ++r) acc = fma4(bcast_lane(Nu_l[r], t), R[r], acc);
-            const float rw = recip(acc.w);
-            if (act) {
-                float* o = pts + 3 * ((size_t)(a0 + t) * s.nv_s + b);
-                o[0] = acc.x * rw;
-                o[1] = acc.y * rw;
-                o[2] = acc.z * rw;
-            }
-        }
-    }
+    Block bk = make_block(lds->blk, j0, ncols, P);
+    float* orow = pts + 3 * ((size_t)row0 * s.nv_s + b);
+    const size_t ostride = 3 * (size_t)s.nv_s;
+    if (bk.on)
+        fwd_rows<P, QM, true>(s, bk, Nv, q, jb, act, row0, row1, in.u0, orow, ostride);
+    else
+        fwd_rows<P, QM, false>(s, bk, Nv, q, jb, act, row0, row1, in.u0, orow, ostride);
 }
 
 // --------------------------------------------------------------------------
@@ -297,28 +334,31 @@ struct BwdState {
     int key_off;      // kb - kfirst for active lanes
     int nkeys;        // distinct keys span kfirst..klast
     int j0, ncols;    // rect column range
-    int seg_first;    // first lane of this lane's segment
-    int nsteps;       // scan steps needed (max segment length)
+    int nsteps;       // in-row scan steps needed (ceil log2 of the longest run in a row)
+    bool cross;       // some segment crosses a 16-lane row boundary
+    float m[6];       // per-step "same segment as the source lane" multipliers
     bool head;        // last lane of its segment
     int q;            // degree in v (uniform, <= QM)
     float f[QM + 1];  // dL/dNv_h(v_b) partial
 };
 
-// per-wave LDS of the backward tile, sized for degrees p <= PM, q <= QM
+// per-wave LDS of the backward tile, sized for degrees p <= PM
 template <int PM, int QM>
 struct BwdLdsT {
+    float4 blk[kBlkCap];
     float knots[2][kWG];
-    float4 ring[kRingCap];
-    float4 col[kWave * (QM + 1)];           // segment sums, [head lane][h]
+    float4 col[kWave];                      // run sums of one h, [head lane]
+    float3 g[kGRows][kWave];                // staged dL/dS rows
     short head_of[kWG];                     // key offset -> head lane, or -1
     float ebuf[kEBatch * 4 * (PM + 1)];     // 16-lane partials of dL/dNu
 };
 
 // pointers into one wave's BwdLdsT
 struct BwdLds {
+    float4* blk;
     float* knots[2];
-    float4* ring;
     float4* col;
+    float3* g;
     short* head_of;
     float* ebuf;
 };
@@ -326,26 +366,51 @@ struct BwdLds {
 template <int PM, int QM>
 __device__ __forceinline__ BwdLds bwd_lds(BwdLdsT<PM, QM>* t) {
     BwdLds l;
+    l.blk = t->blk;
     l.knots[0] = t->knots[0];
     l.knots[1] = t->knots[1];
-    l.ring = t->ring;
     l.col = t->col;
+    l.g = &t->g[0][0];
     l.head_of = t->head_of;
     l.ebuf = t->ebuf;
     return l;
 }
 
-// Flush control row i (accumulator G) of the tile: dV partial and the rect
-// row i - i0 of dL/dPw.
+// One step of a segmented inclusive scan with DPP: x += m * x[source].
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float seg_step(float x, float m) {
+    const float y = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWMASK, 0xF, true));
+    return __builtin_fmaf(y, m, x);
+}
+
+// Segmented inclusive scan over the wave (segments are runs of equal
+// v-span): in-row Hillis-Steele steps (row_shr 1, 2, 4, 8), then the
+// row_bcast 15 / 31 steps that carry runs across 16-lane rows.  After it,
+// the last lane of each run holds the run's sum.  Fixed order: deterministic.
 template <int QM>
-__device__ __forceinline__ void flush_row(const Surf& s, BwdState<QM>& st, const Ring& rg, int i, int i0,
+__device__ __forceinline__ float seg_scan(float x, const BwdState<QM>& st) {
+    if (st.nsteps > 0) x = seg_step<0x111, 0xF>(x, st.m[0]);
+    if (st.nsteps > 1) x = seg_step<0x112, 0xF>(x, st.m[1]);
+    if (st.nsteps > 2) x = seg_step<0x114, 0xF>(x, st.m[2]);
+    if (st.nsteps > 3) x = seg_step<0x118, 0xF>(x, st.m[3]);
+    if (st.cross) {
+        x = seg_step<0x142, 0xA>(x, st.m[4]);
+        x = seg_step<0x143, 0xC>(x, st.m[5]);
+    }
+    return x;
+}
+
+// Flush control row i (accumulator G) of the tile: dV partial and the rect
+// row i - i0 of dL/dPw.  Row i is staged in the block (or read from global).
+template <int QM, bool BLK>
+__device__ __forceinline__ void flush_row(const Surf& s, BwdState<QM>& st, const Block& bk, int i, int i0,
                                           float4 G, float4* __restrict__ rect, BwdLds* L, bool want_pw,
                                           bool want_kv) {
-    const int lane = lane_id();
+    const int lane = lane_opaque();
     const int q = st.q;
     if (want_kv) {
-        if (rg.on) {
-            const float4* row = ring_row(rg, i) + (st.jb - rg.j0);
+        if constexpr (BLK) {
+            const float4* row = block_row(bk, i, st.jb);
 #pragma unroll
             for (int h = 0; h <= QM; ++h)
                 if (h <= q) st.f[h] += dot4(row[h], G);
@@ -356,57 +421,48 @@ __device__ __forceinline__ void flush_row(const Surf& s, BwdState<QM>& st, const
         }
     }
     if (!want_pw) return;
-    // segmented inclusive scan over lanes sharing a v-span, one h at a time
+    // control column j0 + c collects, for every h, the run sum of the key
+    // kfirst + c - h; one h at a time through a 64-entry LDS buffer
+    float4 acc0 = make_float4(0.f, 0.f, 0.f, 0.f), acc1 = acc0;
 #pragma unroll
     for (int h = 0; h <= QM; ++h) {
         if (h > q) continue;
         const float c = st.act ? st.Nv[h] : 0.f;
         float4 x = make_float4(c * G.x, c * G.y, c * G.z, c * G.w);
-        for (int step = 0, d = 1; step < st.nsteps; ++step, d <<= 1) {
-            const bool take = (lane - d) >= st.seg_first;
-            float4 y;
-            y.x = __shfl_up(x.x, d, kWave);
-            y.y = __shfl_up(x.y, d, kWave);
-            y.z = __shfl_up(x.z, d, kWave);
-            y.w = __shfl_up(x.w, d, kWave);
-            if (take) {
-                x.x += y.x;
-                x.y += y.y;
-                x.z += y.z;
-                x.w += y.w;
-            }
-        }
-        if (st.head) L->col[lane * (QM + 1) + h] = x;
-    }
-    wave_lds_sync();
-    // control column j = j0 + c gathers keys kfirst + c - h
-    for (int c = lane; c < st.ncols; c += kWave) {
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        x.x = seg_scan<QM>(x.x, st);
+        x.y = seg_scan<QM>(x.y, st);
+        x.z = seg_scan<QM>(x.z, st);
+        x.w = seg_scan<QM>(x.w, st);
+        if (st.head) L->col[lane] = x;
+        wave_lds_sync();
 #pragma unroll
-        for (int h = 0; h <= QM; ++h) {
-            const int o = c - h;
-            const int hl = (h <= q && o >= 0 && o < st.nkeys) ? (int)L->head_of[o] : -1;
+        for (int pass = 0; pass < 2; ++pass) {
+            const int o = lane + pass * kWave - h;
+            const int hl = (o >= 0 && o < st.nkeys) ? (int)L->head_of[o] : -1;
             if (hl >= 0) {
-                const float4 v = L->col[hl * (QM + 1) + h];
+                const float4 v = L->col[hl];
+                float4& acc = pass ? acc1 : acc0;
                 acc.x += v.x;
                 acc.y += v.y;
                 acc.z += v.z;
                 acc.w += v.w;
             }
         }
-        rect[(size_t)(i - i0) * st.ncols + c] = acc;
+        wave_lds_sync();
     }
-    wave_lds_sync();
+    float4* out = rect + (size_t)(i - i0) * st.ncols;
+    if (lane < st.ncols) out[lane] = acc0;
+    if (lane + kWave < st.ncols) out[lane + kWave] = acc1;
 }
 
 // Column set-up of a backward tile (independent of the degree in u): the
 // lane's v-span and basis, and the segment structure of the spans.
 template <int QM>
-__device__ __forceinline__ void bwd_columns(const Surf& s, int q, int col0, BwdState<QM>& st, BwdLds* L) {
+__device__ __forceinline__ void bwd_columns(const Surf& s, int q, int col0, float vb, BwdState<QM>& st, BwdLds* L) {
     const int lane = lane_id();
     st.q = q;
     int j0, ncols;
-    st.kb = tile_columns<QM>(s, q, col0, st.Nv, st.act, j0, ncols);
+    st.kb = tile_columns<QM>(s, q, col0, vb, st.Nv, st.act, j0, ncols);
     st.jb = st.kb - q;
 #pragma unroll
     for (int h = 0; h <= QM; ++h) st.f[h] = 0.f;
@@ -427,13 +483,24 @@ __device__ __forceinline__ void bwd_columns(const Surf& s, int q, int col0, BwdS
             const int y = __shfl_up(f, d, kWave);
             if (lane >= d) f = max(f, y);
         }
-        st.seg_first = st.act ? f : kWave;  // inactive lanes never take
-        int len = st.act ? lane - f + 1 : 1;
+        const int seg_first = st.act ? f : kWave;  // inactive lanes never take
+        // longest run inside one 16-lane row, and whether any run crosses rows
+        const int row0 = lane & ~15;
+        int len = st.act ? lane - max(f, row0) + 1 : 1;
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) len = max(len, __shfl_xor(len, d, kWave));
         int steps = 0;
         while ((1 << steps) < len) ++steps;
         st.nsteps = steps;
+        st.cross = __any(st.act && (lane & 15) == 0 && seg_first < lane);
+        const int lr = lane & 15, row = lane >> 4;
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+            const int d = 1 << s2;
+            st.m[s2] = (lr >= d && lane - d >= seg_first) ? 1.f : 0.f;
+        }
+        st.m[4] = ((row == 1 || row == 3) && 16 * row - 1 >= seg_first) ? 1.f : 0.f;
+        st.m[5] = ((row == 2 || row == 3) && 31 >= seg_first) ? 1.f : 0.f;
     }
     for (int o = lane; o < st.nkeys; o += kWave) L->head_of[o] = (short)-1;
     wave_lds_sync();
@@ -445,7 +512,7 @@ __device__ __forceinline__ void bwd_columns(const Surf& s, int q, int col0, BwdS
 // each (row, r) in a fixed order and store them contiguously.
 template <int P>
 __device__ __forceinline__ void flush_e(BwdLds* L, int nb, float* __restrict__ e_out) {
-    const int lane = lane_id();
+    const int lane = lane_opaque();
     wave_lds_sync();
     for (int idx = lane; idx < nb * (P + 1); idx += kWave) {
         const int t = idx / (P + 1), r = idx - t * (P + 1);
@@ -455,120 +522,107 @@ __device__ __forceinline__ void flush_e(BwdLds* L, int nb, float* __restrict__ e
     wave_lds_sync();
 }
 
-template <int P, int QM>
-__device__ __forceinline__ void bwd_rows(const Surf& s, BwdState<QM>& st, int col0, int row0, int row1,
-                                         const float* __restrict__ gpts, SlotView out, BwdLds* L,
-                                         unsigned mask) {
-    constexpr int D = 4;  // rows of dL/dS in flight
+// Stage dL/dS of rows [a, a + n) (n <= kGRows) of this lane's column:
+// all loads in flight together, then into LDS.
+__device__ __forceinline__ void stage_g(const float* __restrict__ gpts, int a, int n, int nv_s, int b, bool act,
+                                        BwdLds* L) {
+    const int lane = lane_opaque();
+    float3 v[kGRows];
+    const float* gp = gpts + 3 * ((size_t)a * nv_s + b);
+#pragma unroll
+    for (int j = 0; j < kGRows; ++j) {
+        v[j] = make_float3(0.f, 0.f, 0.f);
+        if (act && j < n) v[j] = make_float3(gp[0], gp[1], gp[2]);
+        gp += 3 * (size_t)nv_s;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < kGRows; ++j) L->g[j * kWave + lane] = v[j];
+    wave_lds_sync();
+}
+
+template <int P, int QM, bool BLK>
+__device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, Block& bk, int col0, int row0,
+                                              int row1, float u0, const float* __restrict__ gpts, SlotView out,
+                                              BwdLds* L, unsigned mask) {
     const int lane = lane_id();
     const bool want_pw = (mask & 3u) != 0;
     const bool want_ku = (mask & 4u) != 0;
     const bool want_kv = (mask & 8u) != 0;
     const int q = st.q;
     const int b = col0 + lane;
-    const Ring rg = make_ring(L->ring, st.j0, st.ncols, P);
     float4 R[P + 1], G[P + 1];
-    RowPrefetch pf;
-    int cur = -1, i0 = 0, nxt = 0;
-    // Slide the window until its last row is `target`, flushing every row
-    // that leaves it.  Rows past the last control row are never loaded; the
-    // end-of-tile drain uses this with target = cur + P + 1.
-    auto advance = [&](int target) {
-        while (cur < target) {
-            flush_row<QM>(s, st, rg, cur - P, i0, G[0], out.rect, L, want_pw, want_kv);
-#pragma unroll
-            for (int r = 0; r < P; ++r) {
-                R[r] = R[r + 1];
-                G[r] = G[r + 1];
-            }
-            ++cur;
-            G[P] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (cur < s.nu_c) R[P] = ring_contract<QM>(s, rg, cur, st.jb, st.Nv, q);
-            if (rg.on && nxt < s.nu_c) {
-                wave_lds_sync();
-                store_row(rg, nxt, pf);  // replaces the row just flushed
-                wave_lds_sync();
-                ++nxt;
-                prefetch_row(s, rg, nxt, pf);
-            }
-        }
-    };
-    // dL/dS of the next D rows, in flight while the current rows are processed
-    float3 gq[D];
-    auto load_g = [&](int a) {
-        float3 v = make_float3(0.f, 0.f, 0.f);
-        if (st.act && a < row1) {
-            const float* gp = gpts + 3 * ((size_t)a * s.nv_s + b);
-            v = make_float3(gp[0], gp[1], gp[2]);
-        }
-        return v;
-    };
-#pragma unroll
-    for (int j = 0; j < D; ++j) gq[j] = load_g(row0 + j);
-    float u_next = s.us[min(row0 + lane, row1 - 1)];
+    int cur = -1, i0 = 0;
     for (int a0 = row0; a0 < row1; a0 += kWave) {
         const int nr = min(kWave, row1 - a0);
         float Nu_l[P + 1];
-        const int ka_l = sample_basis<P>(s.ku, s.nu_c, u_next, Nu_l);
-        if (a0 + kWave < row1) u_next = s.us[min(a0 + kWave + lane, row1 - 1)];
+        const float ua = a0 == row0 ? u0 : s.us[a0 + min(lane, nr - 1)];
+        const int ka_l = sample_basis<P>(s.ku, s.nu_c, ua, Nu_l);
         int eb = 0;  // rows in the current dL/dNu batch
-        for (int t0 = 0; t0 < nr; t0 += D) {
+        for (int t = 0; t < nr; ++t) {
+            if ((t & (kGRows - 1)) == 0) stage_g(gpts, a0 + t, min(kGRows, nr - t), s.nv_s, b, st.act, L);
+            const int ka = bcast_lane(ka_l, t);
+            if (cur < 0) {
+                cur = ka;
+                i0 = ka - P;
+                ensure_rows<BLK>(s, bk, ka - P, ka);
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const int t = t0 + j;
-                if (t >= nr) break;
-                const int ka = bcast_lane(ka_l, t);
-                if (cur < 0) {
-                    cur = ka;
-                    i0 = ka - P;
-                    if (rg.on) {
-                        stage_ring<P>(s, rg, ka);
-                        wave_lds_sync();
-                        nxt = ka + 2;
-                        prefetch_row(s, rg, nxt, pf);
-                    }
-#pragma unroll
-                    for (int r = 0; r <= P; ++r) {
-                        R[r] = ring_contract<QM>(s, rg, ka - P + r, st.jb, st.Nv, q);
-                        G[r] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    }
-                } else {
-                    // rows are non-decreasing, so the window only moves forward
-                    advance(ka);
+                for (int r = 0; r <= P; ++r) {
+                    R[r] = blk_contract<QM, BLK>(s, bk, ka - P + r, st.jb, st.Nv, q);
+                    G[r] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                const float3 g = gq[j];
-                gq[j] = load_g(a0 + t + D);
-                float Nu[P + 1];
+            } else {
+                // rows are non-decreasing, so the window only moves forward;
+                // each control row leaving it is flushed
+                while (cur < ka) {
+                    flush_row<QM, BLK>(s, st, bk, cur - P, i0, G[0], out.rect, L, want_pw, want_kv);
 #pragma unroll
-                for (int r = 0; r <= P; ++r) Nu[r] = bcast_lane(Nu_l[r], t);
-                // recompute S' (nothing is saved by the forward)
-                float4 sp = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-                for (int r = 0; r <= P; ++r) sp = fma4(Nu[r], R[r], sp);
-                const float rw = recip(sp.w);
-                const float cx = g.x * rw, cy = g.y * rw, cz = g.z * rw;
-                const float cw = -(cx * sp.x + cy * sp.y + cz * sp.z) * rw;
-                const float4 hv = make_float4(cx, cy, cz, cw);
-#pragma unroll
-                for (int r = 0; r <= P; ++r) G[r] = fma4(Nu[r], hv, G[r]);
-                if (want_ku) {
-#pragma unroll
-                    for (int r = 0; r <= P; ++r) {
-                        const float e = row16_sum(dot4(R[r], hv));
-                        if ((lane & 15) == 0) L->ebuf[(eb * 4 + (lane >> 4)) * (P + 1) + r] = e;
+                    for (int r = 0; r < P; ++r) {
+                        R[r] = R[r + 1];
+                        G[r] = G[r + 1];
                     }
-                    if (++eb == kEBatch) {
-                        flush_e<P>(L, eb, out.e + (size_t)(a0 + t + 1 - eb - row0) * (P + 1));
-                        eb = 0;
-                    }
+                    ++cur;
+                    G[P] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    ensure_rows<BLK>(s, bk, cur - P, cur);
+                    R[P] = blk_contract<QM, BLK>(s, bk, cur, st.jb, st.Nv, q);
+                }
+            }
+            const float3 g = L->g[(t & (kGRows - 1)) * kWave + lane];
+            float Nu[P + 1];
+#pragma unroll
+            for (int r = 0; r <= P; ++r) Nu[r] = bcast_lane(Nu_l[r], t);
+            // recompute S' (nothing is saved by the forward)
+            float4 sp = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int r = 0; r <= P; ++r) sp = fma4(Nu[r], R[r], sp);
+            const float rw = recip(sp.w);
+            const float cx = g.x * rw, cy = g.y * rw, cz = g.z * rw;
+            const float cw = -(cx * sp.x + cy * sp.y + cz * sp.z) * rw;
+            const float4 hv = make_float4(cx, cy, cz, cw);
+#pragma unroll
+            for (int r = 0; r <= P; ++r) G[r] = fma4(Nu[r], hv, G[r]);
+            if (want_ku) {
+#pragma unroll
+                for (int r = 0; r <= P; ++r) {
+                    const float e = row16_sum(dot4(R[r], hv));
+                    if ((lane & 15) == 0) L->ebuf[(eb * 4 + (lane >> 4)) * (P + 1) + r] = e;
+                }
+                if (++eb == kEBatch) {
+                    flush_e<P>(L, eb, out.e + (size_t)(a0 + t + 1 - eb - row0) * (P + 1));
+                    eb = 0;
                 }
             }
         }
         if (want_ku && eb > 0) flush_e<P>(L, eb, out.e + (size_t)(a0 + nr - eb - row0) * (P + 1));
     }
-    // flush the rows still in the window
+    // flush the rows still in the window (all still staged)
     const int i1 = cur;
-    advance(cur + P + 1);
+    for (int r = 0; r <= P; ++r) {
+        flush_row<QM, BLK>(s, st, bk, cur - P, i0, G[0], out.rect, L, want_pw, want_kv);
+#pragma unroll
+        for (int m = 0; m < P; ++m) G[m] = G[m + 1];
+        ++cur;
+    }
     if (want_kv) {
 #pragma unroll
         for (int h = 0; h <= QM; ++h)
@@ -582,35 +636,50 @@ __device__ __forceinline__ void bwd_rows(const Surf& s, BwdState<QM>& st, int co
     }
 }
 
-// Knots of the tile's surface into LDS; returns the surface view that reads them.
-__device__ __forceinline__ Surf bwd_stage_knots(const Surf& sg, int p, int q, BwdLds* L) {
+template <int P, int QM>
+__device__ __forceinline__ void bwd_rows(const Surf& s, BwdState<QM>& st, int col0, int row0, int row1, float u0,
+                                         const float* __restrict__ gpts, SlotView out, BwdLds* L,
+                                         unsigned mask) {
+    Block bk = make_block(L->blk, st.j0, st.ncols, P);
+    if (bk.on)
+        bwd_rows_impl<P, QM, true>(s, st, bk, col0, row0, row1, u0, gpts, out, L, mask);
+    else
+        bwd_rows_impl<P, QM, false>(s, st, bk, col0, row0, row1, u0, gpts, out, L, mask);
+}
+
+// Stage the tile's first inputs (knots into LDS); returns the surface view
+// that reads the knots from LDS.
+__device__ __forceinline__ Surf bwd_stage(const Surf& sg, int p, int q, int col0, int row0, int row1, BwdLds* L,
+                                          TileIn& in) {
     Surf s = sg;
-    s.ku = stage_knots(sg.ku, sg.nu_c + p + 1, L->knots[0]);
-    s.kv = stage_knots(sg.kv, sg.nv_c + q + 1, L->knots[1]);
-    wave_lds_sync();
+    in = stage_tile(sg, p, q, col0, row0, row1, L->knots[0], L->knots[1]);
+    s.ku = L->knots[0];
+    s.kv = L->knots[1];
     return s;
 }
 
 template <int P, int QM>
 __device__ __forceinline__ void bwd_tile(const Surf& sg, int q, int col0, int row0, int row1,
                                          const float* __restrict__ gpts, SlotView out, BwdLds* L, unsigned mask) {
-    const Surf s = bwd_stage_knots(sg, P, q, L);
+    TileIn in;
+    const Surf s = bwd_stage(sg, P, q, col0, row0, row1, L, in);
     BwdState<QM> st;
-    bwd_columns<QM>(s, q, col0, st, L);
-    bwd_rows<P, QM>(s, st, col0, row0, row1, gpts, out, L, mask);
+    bwd_columns<QM>(s, q, col0, in.v, st, L);
+    bwd_rows<P, QM>(s, st, col0, row0, row1, in.u0, gpts, out, L, mask);
 }
 
 // --------------------------------------------------------------------------
-// finalize: one workgroup (kWG threads) per surface
+// finalize: one wave per surface (kWavesPerWG surfaces per workgroup)
 // --------------------------------------------------------------------------
-constexpr int kFinMaxTiles = 256;  // tile headers staged in LDS (more: read from global)
-constexpr int kFinCp = 8;          // control points per thread per pass
+constexpr int kFinMaxTiles = 64;  // tile headers staged in LDS (more: read from global)
+constexpr int kFinCp = 8;         // control points per lane per pass
+constexpr int kFinW = 2 * kMaxDeg + 2;
 
 struct FinLds {
     float knots[kWG];
     int4 hdr[kFinMaxTiles];
-    float contrib[kWG * (2 * kMaxDeg + 2)];  // per sample, knot-window adjoints
-    int span[kWG];
+    float contrib[kWave * kFinW];  // per sample of the chunk, knot-window adjoints
+    int span[kWave];
 };
 
 // Tiles of one surface in natural order (row blocks outer, 64-column blocks
@@ -623,70 +692,88 @@ struct TileRef {
 
 // Knot gradient of one direction: for every sample x_a of the direction,
 // coef(a)[r] = dL/dN_{k_a-D+r}(x_a) is turned into per-knot adjoints by
-// basis_knot_adjoint (FP64); the adjoints are then summed over samples in
-// sample order (chunks of kWG samples staged in LDS), one thread per knot.
+// basis_knot_adjoint; then each knot (one lane per knot) adds the adjoints of
+// the samples whose span window covers it, in sample order (spans are
+// non-decreasing, so those samples are contiguous), accumulating in FP64.
 template <int D, class CoefAt>
 __device__ __forceinline__ void knot_gradient(const float* __restrict__ Ug, int nc, const float* __restrict__ xs,
                                               int ns, CoefAt coef_at, float* __restrict__ gout, FinLds* L) {
     constexpr int W = 2 * D + 2;
-    const int tid = threadIdx.x;
+    const int lane = lane_id();
     const int nk = nc + D + 1;
     const int n = nc - 1;
-    __syncthreads();
-    if (tid < nk) L->knots[tid] = Ug[tid];
-    __syncthreads();
+    wave_lds_sync();
+    for (int i = lane; i < nk; i += kWave) L->knots[i] = Ug[i];
+    wave_lds_sync();
     const float* U = L->knots;
-    double acc = 0.0;
-    for (int a0 = 0; a0 < ns; a0 += kWG) {
-        const int a = a0 + tid;
-        int k = -1;
+    double acc[kWG / kWave];
+#pragma unroll
+    for (int m = 0; m < kWG / kWave; ++m) acc[m] = 0.0;
+    for (int a0 = 0; a0 < ns; a0 += kWave) {
+        const int a = a0 + lane;
+        const int cnt = min(kWave, ns - a0);
+        int k = 0x7fffffff;
         if (a < ns) {
             const float x = clamp_param(U, D, n, xs[a]);
             k = find_span(U, D, n, x);
-            double e[D + 1];
+            float e[D + 1];
             coef_at(a, e);
-            double g[W];
+            float g[W];
             basis_knot_adjoint<D>(U, k, x, e, g);
 #pragma unroll
-            for (int t = 0; t < W; ++t) L->contrib[tid * W + t] = (float)g[t];
+            for (int t = 0; t < W; ++t) L->contrib[lane * W + t] = g[t];
         }
-        L->span[tid] = k;
-        __syncthreads();
-        const int cnt = min(kWG, ns - a0);
-        if (tid < nk) {
-            for (int r = 0; r < cnt; ++r) {
-                const int t = tid - (L->span[r] - D);
-                if (t >= 0 && t < W) acc += (double)L->contrib[r * W + t];
+        L->span[lane] = k;
+        wave_lds_sync();
+#pragma unroll
+        for (int m = 0; m < kWG / kWave; ++m) {
+            const int kk = lane + m * kWave;
+            if (kk < nk) {
+                // first sample of the chunk whose span is >= kk - D - 1
+                int lo = 0, hi = cnt;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (L->span[mid] < kk - D - 1) lo = mid + 1; else hi = mid;
+                }
+                for (int r = lo; r < cnt; ++r) {
+                    const int sp = L->span[r];
+                    if (sp > kk + D) break;
+                    acc[m] += (double)L->contrib[r * W + (kk - (sp - D))];
+                }
             }
         }
-        __syncthreads();
+        wave_lds_sync();
     }
-    if (tid < nk) gout[tid] = (float)acc;
+#pragma unroll
+    for (int m = 0; m < kWG / kWave; ++m) {
+        const int kk = lane + m * kWave;
+        if (kk < nk) gout[kk] = (float)acc[m];
+    }
 }
 
 template <int P, int Q, class TileAt>
 __device__ __forceinline__ void finalize_surface(const Surf& s, int ntiles, TileAt tile_at, float* __restrict__ gctrl,
                                                  float* __restrict__ gw, float* __restrict__ gku,
                                                  float* __restrict__ gkv, unsigned mask, FinLds* L) {
-    const int tid = threadIdx.x;
+    const int lane = lane_id();
     const size_t rect_bytes = 16 * (size_t)s.nu_c * s.nv_c;
     const int ncb = (s.nv_s + kWave - 1) / kWave;
     const int rows = ntiles > 0 ? tile_at(0).alloc_rows : 1;
     const int nrb = ncb > 0 ? ntiles / ncb : 0;
     const bool hdr_lds = ntiles <= kFinMaxTiles;
     if (hdr_lds)
-        for (int t = tid; t < ntiles; t += kWG) L->hdr[t] = *reinterpret_cast<const int4*>(tile_at(t).slot);
-    __syncthreads();
+        for (int t = lane; t < ntiles; t += kWave) L->hdr[t] = *reinterpret_cast<const int4*>(tile_at(t).slot);
+    wave_lds_sync();
     // dL/dP and dL/dw from the tile rectangles, tiles in fixed order
     if (mask & 3u) {
         const int ncp = s.nu_c * s.nv_c;
-        for (int base = 0; base < ncp; base += kWG * kFinCp) {
+        for (int base = 0; base < ncp; base += kWave * kFinCp) {
             float4 acc[kFinCp];
             int ii[kFinCp], jj[kFinCp];
 #pragma unroll
             for (int c = 0; c < kFinCp; ++c) {
                 acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
-                const int ij = base + c * kWG + tid;
+                const int ij = base + c * kWave + lane;
                 ii[c] = ij / s.nv_c;
                 jj[c] = ij - ii[c] * s.nv_c;
             }
@@ -697,7 +784,7 @@ __device__ __forceinline__ void finalize_surface(const Surf& s, int ntiles, Tile
                 const int pitch = h.w - h.z + 1;
 #pragma unroll
                 for (int c = 0; c < kFinCp; ++c) {
-                    const int ij = base + c * kWG + tid;
+                    const int ij = base + c * kWave + lane;
                     if (ij < ncp && ii[c] >= h.x && ii[c] <= h.y && jj[c] >= h.z && jj[c] <= h.w) {
                         const float4 v = rect[(size_t)(ii[c] - h.x) * pitch + (jj[c] - h.z)];
                         acc[c].x += v.x;
@@ -709,7 +796,7 @@ __device__ __forceinline__ void finalize_surface(const Surf& s, int ntiles, Tile
             }
 #pragma unroll
             for (int c = 0; c < kFinCp; ++c) {
-                const int ij = base + c * kWG + tid;
+                const int ij = base + c * kWave + lane;
                 if (ij >= ncp) continue;
                 const float wt = s.w[ij];
                 const float* pc = s.ctrl + 3 * ij;
@@ -724,32 +811,32 @@ __device__ __forceinline__ void finalize_surface(const Surf& s, int ntiles, Tile
     }
     // dL/dU: e(a) = sum over the column blocks of a's row block
     if (mask & 4u) {
-        auto coef = [&](int a, double e[P + 1]) {
+        auto coef = [&](int a, float e[P + 1]) {
 #pragma unroll
-            for (int r = 0; r <= P; ++r) e[r] = 0.0;
+            for (int r = 0; r <= P; ++r) e[r] = 0.0f;
             const int rb = a / rows;
             for (int cb = 0; cb < ncb; ++cb) {
                 const TileRef tr = tile_at(rb * ncb + cb);
                 const float* ev = reinterpret_cast<const float*>(tr.slot + 16 + rect_bytes) +
                                   (size_t)(a - tr.row0) * (P + 1);
 #pragma unroll
-                for (int r = 0; r <= P; ++r) e[r] += (double)ev[r];
+                for (int r = 0; r <= P; ++r) e[r] += ev[r];
             }
         };
         knot_gradient<P>(s.ku, s.nu_c, s.us, s.nu_s, coef, gku, L);
     }
     // dL/dV: f(b) = sum over the row blocks of b's column block
     if (mask & 8u) {
-        auto coef = [&](int b, double f[Q + 1]) {
+        auto coef = [&](int b, float f[Q + 1]) {
 #pragma unroll
-            for (int h = 0; h <= Q; ++h) f[h] = 0.0;
+            for (int h = 0; h <= Q; ++h) f[h] = 0.0f;
             const int cb = b / kWave;
             for (int rb = 0; rb < nrb; ++rb) {
                 const TileRef tr = tile_at(rb * ncb + cb);
                 const float* fv = reinterpret_cast<const float*>(
                     tr.slot + 16 + rect_bytes + align16(sizeof(float) * (size_t)tr.alloc_rows * (P + 1)));
 #pragma unroll
-                for (int h = 0; h <= Q; ++h) f[h] += (double)fv[(b - tr.col0) * (Q + 1) + h];
+                for (int h = 0; h <= Q; ++h) f[h] += fv[(b - tr.col0) * (Q + 1) + h];
             }
         };
         knot_gradient<Q>(s.kv, s.nv_c, s.vs, s.nv_s, coef, gkv, L);

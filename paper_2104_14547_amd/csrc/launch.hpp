@@ -31,16 +31,29 @@ struct DevTile {
     long long slot_off;  // backward: byte offset of the tile's workspace slot
 };
 
+// Everything a wave needs to start a tile, in one record: the surface's
+// shape and array offsets and the tile's range (26 words, fetched with one
+// vector load, one word per lane).
+struct ExecTile {
+    int p, q, nu_c, nv_c, nu_s, nv_s;
+    int col0, row0, row1;
+    int rows;  // rows per backward tile of the surface (workspace slot layout)
+    long long ctrl_off, w_off, ku_off, kv_off, us_off, vs_off, pts_off;
+    long long slot_off;  // backward: byte offset of the tile's workspace slot
+};
+static_assert(sizeof(ExecTile) == 104, "ExecTile layout");
+
 struct PlanArgs {
     const DevDesc* desc;
-    const DevTile* tiles;  // natural order
-    const int* order;      // execution order (indices into tiles)
+    const DevTile* tiles;     // natural order (finalize)
+    const ExecTile* exec;     // execution records; wave w runs exec[wave_begin[w] .. wave_begin[w + 1])
+    const int* wave_begin;    // [nwaves + 1], assigned at plan creation
     int ntiles;
-    unsigned* counter;     // [0] = next tile, [1] = finished waves
-    int nwaves;            // persistent waves in the grid
+    int nwaves;               // persistent waves in the grid (grid * kWavesPerWG)
     unsigned flags;
     int* err;
     const float *ctrl, *w, *ku, *kv, *us, *vs;
+    int nsurf;             // surfaces in the plan
 };
 
 // uniform batch, one entry per degree in u (defined in k_uniform_p<P>.hip)
@@ -75,6 +88,8 @@ ND_DECLARE_PLAN(7)
 #undef ND_DECLARE_PLAN
 
 // test exports
+// zero n floats on stream st (a kernel, so graph capture records no memset)
+hipError_t launch_zero(hipStream_t st, float* p, size_t n);
 hipError_t launch_spans(int p, hipStream_t st, const float* U, int nk, const float* x, int nx, int* spans,
                         float* N);
 
