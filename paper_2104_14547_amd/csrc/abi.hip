@@ -353,7 +353,8 @@ void assign_waves(const std::vector<double>& cost, int nw, std::vector<int>& ord
 namespace {
 // Host half of plan creation: validate the descriptors, cut tiles, assign
 // them to waves and lay out the device tables in *blob.  The device pointers
-// are bound by plan_bind once the blob has a device address.
+// are bound by plan_bind once the blob has a device address.  With blob ==
+// NULL only the sizes (layout, workspace) are worked out.
 int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nurbs_plan** out,
                std::vector<char>* blob, PlanLayout* lay) {
     if (!ctx) return fail(nullptr, NURBS_EINVAL, "ctx is NULL");
@@ -438,9 +439,25 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
     const int occ_f = std::max(occ[0], 1), occ_b = std::max(occ[1], 1);
     pl->grid_fwd = std::max(1, std::min(occ_f * cus, (pl->nf + kWavesPerWG - 1) / kWavesPerWG));
     pl->grid_bwd = std::max(1, std::min(occ_b * cus, (pl->nb + kWavesPerWG - 1) / kWavesPerWG));
+    // table layout (sizes follow from the counts alone)
+    const size_t nwf = (size_t)pl->grid_fwd * kWavesPerWG, nwb = (size_t)pl->grid_bwd * kWavesPerWG;
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t o_desc = 0;
+    const size_t o_ft = o_desc + al(sizeof(DevDesc) * std::max(n, 1));
+    const size_t o_fx = o_ft + al(sizeof(DevTile) * std::max<size_t>(ft.size(), 1));
+    const size_t o_bt = o_fx + al(sizeof(ExecTile) * std::max<size_t>(ft.size(), 1));
+    const size_t o_bx = o_bt + al(sizeof(DevTile) * std::max<size_t>(bt.size(), 1));
+    const size_t o_fb = o_bx + al(sizeof(ExecTile) * std::max<size_t>(bt.size(), 1));
+    const size_t o_bb = o_fb + al(sizeof(int) * (nwf + 1));
+    const size_t total = o_bb + al(sizeof(int) * (nwb + 1));
+    if (!blob) {  // size query: no schedule, no tables
+        *lay = PlanLayout{o_desc, o_ft, o_fx, o_bt, o_bx, o_fb, o_bb, total};
+        *out = pl;
+        return NURBS_OK;
+    }
     std::vector<int> fo, fbeg, bo, bbeg;
-    assign_waves(fcost, pl->grid_fwd * kWavesPerWG, fo, fbeg);
-    assign_waves(bcost, pl->grid_bwd * kWavesPerWG, bo, bbeg);
+    assign_waves(fcost, (int)nwf, fo, fbeg);
+    assign_waves(bcost, (int)nwb, bo, bbeg);
     auto record = [&](const DevTile& t) {
         const DevDesc& x = dd[t.surf];
         ExecTile r;
@@ -451,19 +468,10 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
         return r;
     };
     std::vector<ExecTile> fx, bx;
+    fx.reserve(fo.size());
+    bx.reserve(bo.size());
     for (int i : fo) fx.push_back(record(ft[i]));
     for (int i : bo) bx.push_back(record(bt[i]));
-
-    // upload tables
-    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t o_desc = 0;
-    const size_t o_ft = o_desc + al(sizeof(DevDesc) * std::max(n, 1));
-    const size_t o_fx = o_ft + al(sizeof(DevTile) * std::max<size_t>(ft.size(), 1));
-    const size_t o_bt = o_fx + al(sizeof(ExecTile) * std::max<size_t>(fx.size(), 1));
-    const size_t o_bx = o_bt + al(sizeof(DevTile) * std::max<size_t>(bt.size(), 1));
-    const size_t o_fb = o_bx + al(sizeof(ExecTile) * std::max<size_t>(bx.size(), 1));
-    const size_t o_bb = o_fb + al(sizeof(int) * fbeg.size());
-    const size_t total = o_bb + al(sizeof(int) * bbeg.size());
     blob->assign(total, 0);
     char* hb = blob->data();
     if (n) memcpy(hb + o_desc, dd.data(), sizeof(DevDesc) * n);
@@ -522,7 +530,7 @@ int nurbs_plan_create_in(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned
     nurbs_plan* pl = nullptr;
     if (out) *out = nullptr;
     nurbs_plan* tmp = nullptr;
-    int rc = plan_build(ctx, host, n, flags, &tmp, &blob, &lay);
+    int rc = plan_build(ctx, host, n, flags, &tmp, tables ? &blob : nullptr, &lay);
     if (rc) return rc;
     pl = tmp;
     if (table_bytes_needed) *table_bytes_needed = lay.total;

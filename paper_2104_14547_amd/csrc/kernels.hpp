@@ -338,6 +338,8 @@ struct BwdState {
     bool cross;       // some segment crosses a 16-lane row boundary
     float m[6];       // per-step "same segment as the source lane" multipliers
     bool head;        // last lane of its segment
+    bool wide;        // the tile touches more than 64 - QM control columns (second gather pass)
+    unsigned hl[2];   // bytes: head lane of key (lane - h) for h = 0..7, 0xFF = none
     int q;            // degree in v (uniform, <= QM)
     float f[QM + 1];  // dL/dNv_h(v_b) partial
 };
@@ -376,28 +378,37 @@ __device__ __forceinline__ BwdLds bwd_lds(BwdLdsT<PM, QM>* t) {
     return l;
 }
 
-// One step of a segmented inclusive scan with DPP: x += m * x[source].
+// One step of a segmented inclusive scan with DPP on the four components
+// at once (independent moves, so their latencies overlap):
+// x += m * x[source lane].
 template <int CTRL, int ROWMASK>
-__device__ __forceinline__ float seg_step(float x, float m) {
-    const float y = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWMASK, 0xF, true));
-    return __builtin_fmaf(y, m, x);
+__device__ __forceinline__ void seg_step4(float4& x, float m) {
+    auto mv = [](float v) {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, true));
+    };
+    const float yx = mv(x.x), yy = mv(x.y), yz = mv(x.z), yw = mv(x.w);
+    x.x = __builtin_fmaf(yx, m, x.x);
+    x.y = __builtin_fmaf(yy, m, x.y);
+    x.z = __builtin_fmaf(yz, m, x.z);
+    x.w = __builtin_fmaf(yw, m, x.w);
 }
 
 // Segmented inclusive scan over the wave (segments are runs of equal
 // v-span): in-row Hillis-Steele steps (row_shr 1, 2, 4, 8), then the
 // row_bcast 15 / 31 steps that carry runs across 16-lane rows.  After it,
-// the last lane of each run holds the run's sum.  Fixed order: deterministic.
+// the last lane of each run holds the run's sum.  The step count and the
+// cross-row flag are wave-uniform, so the steps are taken or skipped by
+// scalar branches.  Fixed order: deterministic.
 template <int QM>
-__device__ __forceinline__ float seg_scan(float x, const BwdState<QM>& st) {
-    if (st.nsteps > 0) x = seg_step<0x111, 0xF>(x, st.m[0]);
-    if (st.nsteps > 1) x = seg_step<0x112, 0xF>(x, st.m[1]);
-    if (st.nsteps > 2) x = seg_step<0x114, 0xF>(x, st.m[2]);
-    if (st.nsteps > 3) x = seg_step<0x118, 0xF>(x, st.m[3]);
+__device__ __forceinline__ void seg_scan4(float4& x, const BwdState<QM>& st) {
+    if (st.nsteps > 0) seg_step4<0x111, 0xF>(x, st.m[0]);
+    if (st.nsteps > 1) seg_step4<0x112, 0xF>(x, st.m[1]);
+    if (st.nsteps > 2) seg_step4<0x114, 0xF>(x, st.m[2]);
+    if (st.nsteps > 3) seg_step4<0x118, 0xF>(x, st.m[3]);
     if (st.cross) {
-        x = seg_step<0x142, 0xA>(x, st.m[4]);
-        x = seg_step<0x143, 0xC>(x, st.m[5]);
+        seg_step4<0x142, 0xA>(x, st.m[4]);
+        seg_step4<0x143, 0xC>(x, st.m[5]);
     }
-    return x;
 }
 
 // Flush control row i (accumulator G) of the tile: dV partial and the rect
@@ -429,23 +440,28 @@ __device__ __forceinline__ void flush_row(const Surf& s, BwdState<QM>& st, const
         if (h > q) continue;
         const float c = st.act ? st.Nv[h] : 0.f;
         float4 x = make_float4(c * G.x, c * G.y, c * G.z, c * G.w);
-        x.x = seg_scan<QM>(x.x, st);
-        x.y = seg_scan<QM>(x.y, st);
-        x.z = seg_scan<QM>(x.z, st);
-        x.w = seg_scan<QM>(x.w, st);
+        seg_scan4<QM>(x, st);
         if (st.head) L->col[lane] = x;
         wave_lds_sync();
-#pragma unroll
-        for (int pass = 0; pass < 2; ++pass) {
-            const int o = lane + pass * kWave - h;
-            const int hl = (o >= 0 && o < st.nkeys) ? (int)L->head_of[o] : -1;
+        {   // first 64 columns: head lane from the per-tile table
+            const int hl = (int)((st.hl[h >> 2] >> (8 * (h & 3))) & 0xFFu);
+            if (hl != 0xFF) {
+                const float4 v = L->col[hl];
+                acc0.x += v.x;
+                acc0.y += v.y;
+                acc0.z += v.z;
+                acc0.w += v.w;
+            }
+        }
+        if (st.wide) {  // columns 64.. (rare)
+            const int o = lane + kWave - h;
+            const int hl = o < st.nkeys ? (int)L->head_of[o] : -1;
             if (hl >= 0) {
                 const float4 v = L->col[hl];
-                float4& acc = pass ? acc1 : acc0;
-                acc.x += v.x;
-                acc.y += v.y;
-                acc.z += v.z;
-                acc.w += v.w;
+                acc1.x += v.x;
+                acc1.y += v.y;
+                acc1.z += v.z;
+                acc1.w += v.w;
             }
         }
         wave_lds_sync();
@@ -491,8 +507,8 @@ __device__ __forceinline__ void bwd_columns(const Surf& s, int q, int col0, floa
         for (int d = 1; d < kWave; d <<= 1) len = max(len, __shfl_xor(len, d, kWave));
         int steps = 0;
         while ((1 << steps) < len) ++steps;
-        st.nsteps = steps;
-        st.cross = __any(st.act && (lane & 15) == 0 && seg_first < lane);
+        st.nsteps = uniform(steps);
+        st.cross = uniform((int)__any(st.act && (lane & 15) == 0 && seg_first < lane)) != 0;
         const int lr = lane & 15, row = lane >> 4;
 #pragma unroll
         for (int s2 = 0; s2 < 4; ++s2) {
@@ -506,6 +522,17 @@ __device__ __forceinline__ void bwd_columns(const Surf& s, int q, int col0, floa
     wave_lds_sync();
     if (st.head) L->head_of[st.key_off] = (short)lane;
     wave_lds_sync();
+    // control column j0 + lane + h collects key lane (offset lane) at degree index h:
+    // its head lane per h, for the first 64 columns
+    st.hl[0] = st.hl[1] = 0xFFFFFFFFu;
+#pragma unroll
+    for (int h = 0; h <= QM; ++h) {
+        const int o = lane - h;
+        const int v = (o >= 0 && o < st.nkeys) ? (int)L->head_of[o] : -1;
+        const unsigned byte = v >= 0 ? (unsigned)v : 0xFFu;
+        st.hl[h >> 2] = (st.hl[h >> 2] & ~(0xFFu << (8 * (h & 3)))) | (byte << (8 * (h & 3)));
+    }
+    st.wide = uniform((int)(st.nkeys + QM > kWave)) != 0;
 }
 
 // Finish a batch of nb rows of dL/dNu: add the four 16-lane partials of

@@ -5,9 +5,12 @@ control points, weights and knots).
 One step: S = surface(P, W, U, V) on the sample grid (library forward),
 g = dL/dS = 2 (S - T) for L = sum ||S - T||^2, the library's backward for
 dL/dP, dL/dW, dL/dU, dL/dV, an Adam update, then the projections that keep
-the surface valid: weights at least ``w_min``, the clamped end knots fixed
-and the interior knots non-decreasing inside [0, 1] (a running maximum, so
-each knot keeps its Adam moments).
+the surface valid: weights at least ``w_min``, the clamped end knots fixed,
+and the interior knots kept in order inside [0, 1] with gaps of at least
+``knot_gap`` (so no span collapses and the knot derivative, which scales
+with the inverse square of a span, stays finite).  The projection is a
+running maximum and a running minimum, so each knot keeps its index and its
+Adam moments.
 
 With ``graph=True`` the whole step (both library launches, the loss gradient,
 Adam and the projections) is captured once in a HIP graph and replayed, so a
@@ -21,6 +24,16 @@ from . import _native as N
 from .api import surface_bwd, surface_fwd
 
 
+def project_knots(inner, ramp, top: float):
+    """In place: the closest-from-below ordering of the interior knots x_1..x_n
+    with x_1 >= g, x_{i+1} >= x_i + g and x_n <= 1 - g (ramp = i * g,
+    top = 1 - (n + 1) g): a running maximum of x_i - i g (floored at 0)
+    pushes knots up, then a running minimum from the right caps them."""
+    lo = torch.cummax(torch.clamp(inner - ramp, min=0.0), 0).values
+    hi = torch.flip(torch.cummin(torch.flip(torch.clamp(lo, max=top), [0]), 0).values, [0])
+    inner.copy_(hi + ramp)
+
+
 class SurfaceFit:
     """Fit one surface of degree (p, q) to a target grid.
 
@@ -29,7 +42,7 @@ class SurfaceFit:
     """
 
     def __init__(self, ctrl, w, ku, kv, p: int, q: int, us, vs, target, lr: float = 1e-2,
-                 train_knots: bool = True, w_min: float = 1e-3, graph: bool = True):
+                 train_knots: bool = True, w_min: float = 1e-3, knot_gap: float = 1e-3, graph: bool = True):
         self.p, self.q = int(p), int(q)
         self.ctrl = ctrl.detach().clone().contiguous()
         self.w = w.detach().clone().contiguous()
@@ -40,6 +53,13 @@ class SurfaceFit:
         self.train_knots = bool(train_knots)
         self.w_min = float(w_min)
         self.nu_c, self.nv_c = int(ctrl.shape[0]), int(ctrl.shape[1])
+        # ramps i * gap (i = 1..n) of the knot projection, one per direction
+        self.ramps = []
+        for d, nc in ((self.p, self.nu_c), (self.q, self.nv_c)):
+            n = nc - d - 1
+            gap = min(float(knot_gap), 0.5 / (n + 1)) if n > 0 else 0.0
+            r = torch.arange(1, n + 1, dtype=torch.float32, device=ctrl.device) * gap
+            self.ramps.append((r, 1.0 - (n + 1) * gap))
         self.mask = N.NURBS_GRAD_CTRL | N.NURBS_GRAD_W
         params = [self.ctrl, self.w]
         if self.train_knots:
@@ -78,10 +98,10 @@ class SurfaceFit:
         with torch.no_grad():
             self.w.clamp_(min=self.w_min)
             if self.train_knots:
-                for U, d, nc in ((self.ku, self.p, self.nu_c), (self.kv, self.q, self.nv_c)):
-                    inner = U[d + 1:nc]
-                    inner.clamp_(0.0, 1.0)
-                    inner.copy_(torch.cummax(inner, 0).values)
+                for U, d, nc, (ramp, top) in ((self.ku, self.p, self.nu_c, self.ramps[0]),
+                                              (self.kv, self.q, self.nv_c, self.ramps[1])):
+                    if nc - d - 1 > 0:
+                        project_knots(U[d + 1:nc], ramp, top)
 
     def _capture(self):
         side = torch.cuda.Stream()

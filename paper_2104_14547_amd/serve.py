@@ -33,6 +33,7 @@ from __future__ import annotations
 
 import collections
 import ctypes
+import gc
 import threading
 import time
 from concurrent.futures import Future
@@ -471,16 +472,25 @@ def run_load(server, requests, rate: float | None, seed: int = 5):
     rng = np.random.Generator(np.random.PCG64(seed))
     n = len(requests)
     gaps = rng.exponential(1.0 / rate, n) if rate else np.zeros(n)
-    t0 = time.perf_counter()
-    arrivals = t0 + np.cumsum(gaps)
-    futs = []
-    for (s, us, vs, T), ta in zip(requests, arrivals):
-        now = time.perf_counter()
-        if ta > now:
-            time.sleep(ta - now)
-        futs.append(server.submit(s, us, vs, T, t_arrival=float(ta)))
-    results = [f.result() for f in futs]
-    t1 = time.perf_counter()
+    # no cyclic garbage collection while the clock runs: its pauses (tens of
+    # ms) would show up as latency of whichever requests were in flight
+    gc.collect()
+    gc_was_on = gc.isenabled()
+    gc.disable()
+    try:
+        t0 = time.perf_counter()
+        arrivals = t0 + np.cumsum(gaps)
+        futs = []
+        for (s, us, vs, T), ta in zip(requests, arrivals):
+            now = time.perf_counter()
+            if ta > now:
+                time.sleep(ta - now)
+            futs.append(server.submit(s, us, vs, T, t_arrival=float(ta)))
+        results = [f.result() for f in futs]
+        t1 = time.perf_counter()
+    finally:
+        if gc_was_on:
+            gc.enable()
     lat = np.array([r.latency for r in results])
     pts = sum(len(r[1]) * len(r[2]) for r in requests)
     return {"requests": n, "rate_offered": rate, "seconds": t1 - t0, "req_per_s": n / (t1 - t0),

@@ -92,8 +92,12 @@ def oracle_fit(s, steps, train_knots=True, w_min=1e-3, b1=0.9, b2=0.999, eps=1e-
         np.maximum(Wt, w_min, out=Wt)
         if train_knots:
             for K, d, nc in ((U, p, nu_c), (V, q, nv_c)):
-                inner = np.clip(K[d + 1:nc], 0.0, 1.0)
-                K[d + 1:nc] = np.maximum.accumulate(inner)
+                n = nc - d - 1
+                gap = min(1e-3, 0.5 / (n + 1))
+                ramp = np.arange(1, n + 1) * gap
+                lo = np.maximum.accumulate(np.maximum(K[d + 1:nc] - ramp, 0.0))
+                hi = np.minimum.accumulate(np.minimum(lo, 1.0 - (n + 1) * gap)[::-1])[::-1]
+                K[d + 1:nc] = hi + ramp
     S = O.surface_fwd(P, Wt, U, V, p, q, us, vs, local=True)
     losses.append(float(((S - Tg) ** 2).sum()))
     return losses
@@ -125,5 +129,6 @@ def test_projections_hold_after_many_steps():
     assert Wt.min() >= 1e-3
     p, q, nu_c, nv_c = s["p"], s["q"], s["nu_c"], s["nv_c"]
     for K, d, nc, K0 in ((U, p, nu_c, s["ku"]), (V, q, nv_c, s["kv"])):
+        assert np.all(np.diff(K[d:nc + 1]) >= 1e-3 * (1 - 1e-3))  # interior gaps kept (FP32)
         assert np.all(np.diff(K) >= 0)
         assert np.array_equal(K[: d + 1], K0[: d + 1]) and np.array_equal(K[nc:], K0[nc:])

@@ -58,3 +58,24 @@ def test_max_requests_and_fixed_bytes():
 def test_empty_queue():
     a = Admission(capacity=10, max_requests=3)
     assert a.take(collections.deque()) == []
+
+
+def test_knot_projection_orders_and_spaces():
+    import numpy as np
+    import torch
+    from paper_2104_14547_amd.fit import project_knots
+    rng = np.random.Generator(np.random.PCG64(0))
+    for n in (1, 5, 60):
+        gap = min(1e-3, 0.5 / (n + 1))
+        ramp = torch.arange(1, n + 1, dtype=torch.float64) * gap
+        for _ in range(20):
+            x = torch.from_numpy(rng.uniform(-0.5, 1.5, n))
+            y = x.clone()
+            project_knots(y, ramp, 1.0 - (n + 1) * gap)
+            full = torch.cat([torch.zeros(1, dtype=y.dtype), y, torch.ones(1, dtype=y.dtype)])
+            assert torch.all(full[1:] - full[:-1] >= gap * (1 - 1e-9))
+        # an already valid vector is left alone
+        ok = torch.linspace(0, 1, n + 2, dtype=torch.float64)[1:-1]
+        z = ok.clone()
+        project_knots(z, ramp, 1.0 - (n + 1) * gap)
+        assert torch.allclose(z, ok, rtol=0, atol=1e-12)
