@@ -40,6 +40,8 @@ struct nurbs_plan {
     ExecTile* d_bexec = nullptr;  // backward execution records, wave order
     int* d_fbegin = nullptr;      // wave boundaries in d_fexec
     int* d_bbegin = nullptr;      // wave boundaries in d_bexec
+    int2* d_fin = nullptr;        // finalize parts (surface, part), most expensive first
+    int nfin = 0;
     int nf = 0, nb = 0;
     int grid_fwd = 0, grid_bwd = 0;
     size_t ws_bytes = 0;
@@ -54,7 +56,7 @@ struct nurbs_plan {
 
 // byte offsets of the device tables inside one allocation
 struct PlanLayout {
-    size_t desc, ftiles, fexec, btiles, bexec, fbegin, bbegin, total;
+    size_t desc, ftiles, fexec, btiles, bexec, fbegin, bbegin, fin, total;
 };
 
 namespace {
@@ -287,6 +289,8 @@ int nurbs_surface_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, c
     const size_t need = kWsHeader + (size_t)g.tiles_b * g.slot;
     if (!ws || ws_bytes < need) return fail(ctx, NURBS_EWORKSPACE, "workspace too small: need " + std::to_string(need));
     if (g.tiles_b > (1ll << 30)) return fail(ctx, NURBS_EINVAL, "batch too large");
+    const long long fin_items = (long long)B * fin_parts(nu_c, nv_c);
+    if (fin_items > (1ll << 30)) return fail(ctx, NURBS_EINVAL, "batch too large");
     UniformArgs a = make_uargs(ctx, g, true, B, nu_c, nv_c, nu_s, nv_s, ctrl, w, ku, kv, us, vs, uv_shared, ws);
     char* slots = reinterpret_cast<char*>(ws) + kWsHeader;
     const dim3 grid((unsigned)((g.tiles_b + kWavesPerWG - 1) / kWavesPerWG));
@@ -296,7 +300,8 @@ int nurbs_surface_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, c
     case P:                                                                                               \
         e = launch_uniform_bwd_p##P(q, grid, st, a, grad_pts, slots, g.slot, grad_mask);                  \
         if (e == hipSuccess)                                                                              \
-            e = launch_uniform_fin_p##P(q, dim3((B + kWavesPerWG - 1) / kWavesPerWG), st, a, slots, g.slot,  \
+            e = launch_uniform_fin_p##P(q, dim3((fin_items + kWavesPerWG - 1) / kWavesPerWG), st, a, slots,  \
+                                        g.slot,                                                           \
                                         grad_ctrl, grad_w, grad_ku,                                       \
                                         grad_kv, grad_mask);                                              \
         break;
@@ -439,6 +444,33 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
     const int occ_f = std::max(occ[0], 1), occ_b = std::max(occ[1], 1);
     pl->grid_fwd = std::max(1, std::min(occ_f * cus, (pl->nf + kWavesPerWG - 1) / kWavesPerWG));
     pl->grid_bwd = std::max(1, std::min(occ_b * cus, (pl->nb + kWavesPerWG - 1) / kWavesPerWG));
+    // finalize parts, most expensive first (estimated dependent memory rounds)
+    std::vector<int2> fin;
+    std::vector<double> fin_cost;
+    for (int s = 0; s < n; ++s) {
+        const nurbs_desc& d = pl->host[s];
+        const int ncb = (d.nv_s + kWave - 1) / kWave;
+        const int nrb = dd[s].tile_count > 0 && ncb > 0 ? dd[s].tile_count / ncb : 0;
+        const int np = fin_parts(d.nu_c, d.nv_c);
+        for (int part = 0; part < np; ++part) {
+            double c;
+            if (part == kFinKU) c = 4.0 + ((d.nu_s + kWave - 1) / kWave) * (2.0 + ncb + 0.2 * (d.p + 1));
+            else if (part == kFinKV) c = 4.0 + ((d.nv_s + kWave - 1) / kWave) * (2.0 + nrb + 0.2 * (d.q + 1));
+            else c = 3.0 + dd[s].tile_count;
+            fin.push_back(make_int2(s, part));
+            fin_cost.push_back(c);
+        }
+    }
+    {
+        std::vector<int> idx(fin.size());
+        std::iota(idx.begin(), idx.end(), 0);
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return fin_cost[x] > fin_cost[y]; });
+        std::vector<int2> sorted(fin.size());
+        for (size_t i = 0; i < idx.size(); ++i) sorted[i] = fin[idx[i]];
+        fin.swap(sorted);
+    }
+    pl->nfin = (int)fin.size();
+
     // table layout (sizes follow from the counts alone)
     const size_t nwf = (size_t)pl->grid_fwd * kWavesPerWG, nwb = (size_t)pl->grid_bwd * kWavesPerWG;
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -449,9 +481,10 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
     const size_t o_bx = o_bt + al(sizeof(DevTile) * std::max<size_t>(bt.size(), 1));
     const size_t o_fb = o_bx + al(sizeof(ExecTile) * std::max<size_t>(bt.size(), 1));
     const size_t o_bb = o_fb + al(sizeof(int) * (nwf + 1));
-    const size_t total = o_bb + al(sizeof(int) * (nwb + 1));
+    const size_t o_fi = o_bb + al(sizeof(int) * (nwb + 1));
+    const size_t total = o_fi + al(sizeof(int2) * std::max<size_t>(fin.size(), 1));
     if (!blob) {  // size query: no schedule, no tables
-        *lay = PlanLayout{o_desc, o_ft, o_fx, o_bt, o_bx, o_fb, o_bb, total};
+        *lay = PlanLayout{o_desc, o_ft, o_fx, o_bt, o_bx, o_fb, o_bb, o_fi, total};
         *out = pl;
         return NURBS_OK;
     }
@@ -481,7 +514,8 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
     if (!bx.empty()) memcpy(hb + o_bx, bx.data(), sizeof(ExecTile) * bx.size());
     memcpy(hb + o_fb, fbeg.data(), sizeof(int) * fbeg.size());
     memcpy(hb + o_bb, bbeg.data(), sizeof(int) * bbeg.size());
-    *lay = PlanLayout{o_desc, o_ft, o_fx, o_bt, o_bx, o_fb, o_bb, total};
+    if (!fin.empty()) memcpy(hb + o_fi, fin.data(), sizeof(int2) * fin.size());
+    *lay = PlanLayout{o_desc, o_ft, o_fx, o_bt, o_bx, o_fb, o_bb, o_fi, total};
     *out = pl;
     return NURBS_OK;
 }
@@ -495,6 +529,7 @@ void plan_bind(nurbs_plan* pl, void* dev, const PlanLayout& lay) {
     pl->d_bexec = reinterpret_cast<ExecTile*>(base + lay.bexec);
     pl->d_fbegin = reinterpret_cast<int*>(base + lay.fbegin);
     pl->d_bbegin = reinterpret_cast<int*>(base + lay.bbegin);
+    pl->d_fin = reinterpret_cast<int2*>(base + lay.fin);
 }
 }  // namespace
 
@@ -591,6 +626,8 @@ PlanArgs plan_args(nurbs_plan* pl, bool bwd, void* ws, const float* ctrl, const 
     a.err = (pl->flags & NURBS_VALIDATE) ? reinterpret_cast<int*>(ws) : nullptr;
     a.ctrl = ctrl; a.w = w; a.ku = ku; a.kv = kv; a.us = us; a.vs = vs;
     a.nsurf = pl->n;
+    a.fin_items = pl->d_fin;
+    a.nfin = pl->nfin;
     return a;
 }
 }  // namespace
@@ -645,10 +682,10 @@ int nurbs_plan_bwd(nurbs_plan* pl, const float* ctrl, const float* w, const floa
     if (ev && e == hipSuccess) e = hipEventRecord(ev[1], st);
     if (e == hipSuccess)
         e = pl->maxd == 5
-                ? launch_plan_fin_d5(dim3((pl->n + kWavesPerWG - 1) / kWavesPerWG), st, a, slots, grad_ctrl, grad_w,
-                                     grad_ku, grad_kv, grad_mask)
-                : launch_plan_fin_d7(dim3((pl->n + kWavesPerWG - 1) / kWavesPerWG), st, a, slots, grad_ctrl, grad_w,
-                                     grad_ku, grad_kv, grad_mask);
+                ? launch_plan_fin_d5(dim3((pl->nfin + kWavesPerWG - 1) / kWavesPerWG), st, a, slots, grad_ctrl,
+                                     grad_w, grad_ku, grad_kv, grad_mask)
+                : launch_plan_fin_d7(dim3((pl->nfin + kWavesPerWG - 1) / kWavesPerWG), st, a, slots, grad_ctrl,
+                                     grad_w, grad_ku, grad_kv, grad_mask);
     if (ev && e == hipSuccess) e = hipEventRecord(ev[2], st);
     if (e != hipSuccess) return hip_fail(pl->ctx, e, "launch plan backward");
     return NURBS_OK;

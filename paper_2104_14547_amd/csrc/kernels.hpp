@@ -778,95 +778,143 @@ __device__ __forceinline__ void knot_gradient(const float* __restrict__ Ug, int 
     }
 }
 
-template <int P, int Q, class TileAt>
-__device__ __forceinline__ void finalize_surface(const Surf& s, int ntiles, TileAt tile_at, float* __restrict__ gctrl,
-                                                 float* __restrict__ gw, float* __restrict__ gku,
-                                                 float* __restrict__ gkv, unsigned mask, FinLds* L) {
+// Finalize work of one surface, in parts that can run on different waves:
+//   kFinPW + c : dL/dP, dL/dw of control points [c * kFinChunk, (c + 1) * kFinChunk)
+//   kFinKU     : dL/dU;   kFinKV : dL/dV.
+constexpr int kFinChunk = kWave * kFinCp;  // control points per dP/dW part
+constexpr int kFinKU = 0, kFinKV = 1, kFinPW = 2;
+
+// Sum of the tile rectangles over this lane's control points of one chunk,
+// tiles in fixed order (each tile's kFinCp loads per lane in flight together).
+template <class TileAt>
+__device__ __forceinline__ void fin_pw_chunk(const Surf& s, int ntiles, TileAt tile_at, int chunk,
+                                             float* __restrict__ gctrl, float* __restrict__ gw, unsigned mask,
+                                             FinLds* L) {
     const int lane = lane_id();
-    const size_t rect_bytes = 16 * (size_t)s.nu_c * s.nv_c;
-    const int ncb = (s.nv_s + kWave - 1) / kWave;
-    const int rows = ntiles > 0 ? tile_at(0).alloc_rows : 1;
-    const int nrb = ncb > 0 ? ntiles / ncb : 0;
     const bool hdr_lds = ntiles <= kFinMaxTiles;
     if (hdr_lds)
         for (int t = lane; t < ntiles; t += kWave) L->hdr[t] = *reinterpret_cast<const int4*>(tile_at(t).slot);
     wave_lds_sync();
-    // dL/dP and dL/dw from the tile rectangles, tiles in fixed order
-    if (mask & 3u) {
-        const int ncp = s.nu_c * s.nv_c;
-        for (int base = 0; base < ncp; base += kWave * kFinCp) {
-            float4 acc[kFinCp];
-            int ii[kFinCp], jj[kFinCp];
+    const int ncp = s.nu_c * s.nv_c;
+    const int base = chunk * kFinChunk;
+    float4 acc[kFinCp];
+    int ii[kFinCp], jj[kFinCp];
 #pragma unroll
-            for (int c = 0; c < kFinCp; ++c) {
-                acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
-                const int ij = base + c * kWave + lane;
-                ii[c] = ij / s.nv_c;
-                jj[c] = ij - ii[c] * s.nv_c;
-            }
-            for (int t = 0; t < ntiles; ++t) {
-                const char* slot = tile_at(t).slot;
-                const int4 h = hdr_lds ? L->hdr[t] : *reinterpret_cast<const int4*>(slot);
-                const float4* rect = reinterpret_cast<const float4*>(slot + 16);
-                const int pitch = h.w - h.z + 1;
+    for (int c = 0; c < kFinCp; ++c) {
+        acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int ij = base + c * kWave + lane;
+        ii[c] = ij / s.nv_c;
+        jj[c] = ij - ii[c] * s.nv_c;
+    }
+    auto add_tile = [&](int t) {
+        const char* slot = tile_at(t).slot;
+        const int4 h = hdr_lds ? L->hdr[t] : *reinterpret_cast<const int4*>(slot);
+        const float4* rect = reinterpret_cast<const float4*>(slot + 16);
+        const int pitch = h.w - h.z + 1;
+        float4 v[kFinCp];
 #pragma unroll
-                for (int c = 0; c < kFinCp; ++c) {
-                    const int ij = base + c * kWave + lane;
-                    if (ij < ncp && ii[c] >= h.x && ii[c] <= h.y && jj[c] >= h.z && jj[c] <= h.w) {
-                        const float4 v = rect[(size_t)(ii[c] - h.x) * pitch + (jj[c] - h.z)];
-                        acc[c].x += v.x;
-                        acc[c].y += v.y;
-                        acc[c].z += v.z;
-                        acc[c].w += v.w;
-                    }
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < kFinCp; ++c) {
-                const int ij = base + c * kWave + lane;
-                if (ij >= ncp) continue;
-                const float wt = s.w[ij];
-                const float* pc = s.ctrl + 3 * ij;
-                if (mask & 1u) {
-                    gctrl[3 * ij + 0] = wt * acc[c].x;
-                    gctrl[3 * ij + 1] = wt * acc[c].y;
-                    gctrl[3 * ij + 2] = wt * acc[c].z;
-                }
-                if (mask & 2u) gw[ij] = pc[0] * acc[c].x + pc[1] * acc[c].y + pc[2] * acc[c].z + acc[c].w;
-            }
+        for (int c = 0; c < kFinCp; ++c) {
+            const int ij = base + c * kWave + lane;
+            const bool in = ij < ncp && ii[c] >= h.x && ii[c] <= h.y && jj[c] >= h.z && jj[c] <= h.w;
+            v[c] = in ? rect[(size_t)(ii[c] - h.x) * pitch + (jj[c] - h.z)] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
+#pragma unroll
+        for (int c = 0; c < kFinCp; ++c) {
+            acc[c].x += v[c].x;
+            acc[c].y += v[c].y;
+            acc[c].z += v[c].z;
+            acc[c].w += v[c].w;
+        }
+    };
+    for (int t = 0; t < ntiles; ++t) add_tile(t);
+#pragma unroll
+    for (int c = 0; c < kFinCp; ++c) {
+        const int ij = base + c * kWave + lane;
+        if (ij >= ncp) continue;
+        const float wt = s.w[ij];
+        const float* pc = s.ctrl + 3 * ij;
+        if (mask & 1u) {
+            gctrl[3 * ij + 0] = wt * acc[c].x;
+            gctrl[3 * ij + 1] = wt * acc[c].y;
+            gctrl[3 * ij + 2] = wt * acc[c].z;
+        }
+        if (mask & 2u) gw[ij] = pc[0] * acc[c].x + pc[1] * acc[c].y + pc[2] * acc[c].z + acc[c].w;
     }
-    // dL/dU: e(a) = sum over the column blocks of a's row block
-    if (mask & 4u) {
-        auto coef = [&](int a, float e[P + 1]) {
+}
+
+// dL/dU: e(a) = sum over the column blocks of a's row block.
+template <int P, int Q, class TileAt>
+__device__ __forceinline__ void fin_knots_u(const Surf& s, int ntiles, TileAt tile_at, float* __restrict__ gku,
+                                            FinLds* L) {
+    const size_t rect_bytes = 16 * (size_t)s.nu_c * s.nv_c;
+    const int ncb = (s.nv_s + kWave - 1) / kWave;
+    const int rows = ntiles > 0 ? tile_at(0).alloc_rows : 1;
+    auto coef = [&](int a, float e[P + 1]) {
 #pragma unroll
-            for (int r = 0; r <= P; ++r) e[r] = 0.0f;
-            const int rb = a / rows;
-            for (int cb = 0; cb < ncb; ++cb) {
-                const TileRef tr = tile_at(rb * ncb + cb);
-                const float* ev = reinterpret_cast<const float*>(tr.slot + 16 + rect_bytes) +
-                                  (size_t)(a - tr.row0) * (P + 1);
+        for (int r = 0; r <= P; ++r) e[r] = 0.0f;
+        const int rb = a / rows;
+        for (int cb = 0; cb < ncb; ++cb) {
+            const TileRef tr = tile_at(rb * ncb + cb);
+            const float* ev = reinterpret_cast<const float*>(tr.slot + 16 + rect_bytes) +
+                              (size_t)(a - tr.row0) * (P + 1);
 #pragma unroll
-                for (int r = 0; r <= P; ++r) e[r] += ev[r];
-            }
-        };
-        knot_gradient<P>(s.ku, s.nu_c, s.us, s.nu_s, coef, gku, L);
+            for (int r = 0; r <= P; ++r) e[r] += ev[r];
+        }
+    };
+    knot_gradient<P>(s.ku, s.nu_c, s.us, s.nu_s, coef, gku, L);
+}
+
+// dL/dV: f(b) = sum over the row blocks of b's column block.
+template <int P, int Q, class TileAt>
+__device__ __forceinline__ void fin_knots_v(const Surf& s, int ntiles, TileAt tile_at, float* __restrict__ gkv,
+                                            FinLds* L) {
+    const size_t rect_bytes = 16 * (size_t)s.nu_c * s.nv_c;
+    const int ncb = (s.nv_s + kWave - 1) / kWave;
+    const int nrb = ncb > 0 ? ntiles / ncb : 0;
+    auto coef = [&](int b, float f[Q + 1]) {
+#pragma unroll
+        for (int h = 0; h <= Q; ++h) f[h] = 0.0f;
+        const int cb = b / kWave;
+        for (int rb = 0; rb < nrb; ++rb) {
+            const TileRef tr = tile_at(rb * ncb + cb);
+            const float* fv = reinterpret_cast<const float*>(
+                tr.slot + 16 + rect_bytes + align16(sizeof(float) * (size_t)tr.alloc_rows * (P + 1)));
+#pragma unroll
+            for (int h = 0; h <= Q; ++h) f[h] += fv[(b - tr.col0) * (Q + 1) + h];
+        }
+    };
+    knot_gradient<Q>(s.kv, s.nv_c, s.vs, s.nv_s, coef, gkv, L);
+}
+
+// One finalize part (see kFinPW / kFinKU / kFinKV).
+template <int P, int Q, class TileAt>
+__device__ __forceinline__ void finalize_part(const Surf& s, int ntiles, TileAt tile_at, int part,
+                                              float* __restrict__ gctrl, float* __restrict__ gw,
+                                              float* __restrict__ gku, float* __restrict__ gkv, unsigned mask,
+                                              FinLds* L) {
+    if (part >= kFinPW) {
+        if (mask & 3u) fin_pw_chunk(s, ntiles, tile_at, part - kFinPW, gctrl, gw, mask, L);
+    } else if (part == kFinKU) {
+        if (mask & 4u) fin_knots_u<P, Q>(s, ntiles, tile_at, gku, L);
+    } else {
+        if (mask & 8u) fin_knots_v<P, Q>(s, ntiles, tile_at, gkv, L);
     }
-    // dL/dV: f(b) = sum over the row blocks of b's column block
-    if (mask & 8u) {
-        auto coef = [&](int b, float f[Q + 1]) {
-#pragma unroll
-            for (int h = 0; h <= Q; ++h) f[h] = 0.0f;
-            const int cb = b / kWave;
-            for (int rb = 0; rb < nrb; ++rb) {
-                const TileRef tr = tile_at(rb * ncb + cb);
-                const float* fv = reinterpret_cast<const float*>(
-                    tr.slot + 16 + rect_bytes + align16(sizeof(float) * (size_t)tr.alloc_rows * (P + 1)));
-#pragma unroll
-                for (int h = 0; h <= Q; ++h) f[h] += fv[(b - tr.col0) * (Q + 1) + h];
-            }
-        };
-        knot_gradient<Q>(s.kv, s.nv_c, s.vs, s.nv_s, coef, gkv, L);
+}
+
+// Number of parts of a surface's finalize.
+__host__ __device__ inline int fin_parts(int nu_c, int nv_c) {
+    return kFinPW + (nu_c * nv_c + kFinChunk - 1) / kFinChunk;
+}
+
+// All parts of one surface on one wave (uniform batches).
+template <int P, int Q, class TileAt>
+__device__ __forceinline__ void finalize_surface(const Surf& s, int ntiles, TileAt tile_at, float* __restrict__ gctrl,
+                                                 float* __restrict__ gw, float* __restrict__ gku,
+                                                 float* __restrict__ gkv, unsigned mask, FinLds* L) {
+    const int np = fin_parts(s.nu_c, s.nv_c);
+    for (int part = 0; part < np; ++part) {
+        finalize_part<P, Q>(s, ntiles, tile_at, part, gctrl, gw, gku, gkv, mask, L);
+        wave_lds_sync();
     }
 }
 

@@ -54,6 +54,8 @@ struct PlanArgs {
     int* err;
     const float *ctrl, *w, *ku, *kv, *us, *vs;
     int nsurf;             // surfaces in the plan
+    const int2* fin_items; // finalize parts (surface, part), most expensive first
+    int nfin;
 };
 
 // uniform batch, one entry per degree in u (defined in k_uniform_p<P>.hip)
