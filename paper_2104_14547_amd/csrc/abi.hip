@@ -402,6 +402,7 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
         const int rb = tile_rows(d.nu_s, d.nv_s, kBwdTilePts);
         x.rows = rb;
         x.tile_first = (int)bt.size();
+        x.slot0 = (long long)(kWsHeader + slot_off);
         int cnt = 0;
         if (d.nu_s > 0 && d.nv_s > 0) {
             for (int r0 = 0; r0 < d.nu_s; r0 += rf)

@@ -399,8 +399,8 @@ __device__ __forceinline__ void seg_step4(float4& x, float m) {
 // the last lane of each run holds the run's sum.  The step count and the
 // cross-row flag are wave-uniform, so the steps are taken or skipped by
 // scalar branches.  Fixed order: deterministic.
-template <int QM>
-__device__ __forceinline__ void seg_scan4(float4& x, const BwdState<QM>& st) {
+template <class S>
+__device__ __forceinline__ void seg_scan4(float4& x, const S& st) {
     if (st.nsteps > 0) seg_step4<0x111, 0xF>(x, st.m[0]);
     if (st.nsteps > 1) seg_step4<0x112, 0xF>(x, st.m[1]);
     if (st.nsteps > 2) seg_step4<0x114, 0xF>(x, st.m[2]);
@@ -409,6 +409,69 @@ __device__ __forceinline__ void seg_scan4(float4& x, const BwdState<QM>& st) {
         seg_step4<0x142, 0xA>(x, st.m[4]);
         seg_step4<0x143, 0xC>(x, st.m[5]);
     }
+}
+
+// Runs of equal keys over the wave (keys non-decreasing with the lane): the
+// multipliers of the DPP segmented scan, its wave-uniform step count and
+// cross-row flag, and whether this lane is the last of its run.
+struct Runs {
+    float m[6];
+    int nsteps;
+    bool cross;
+    bool head;
+};
+
+__device__ __forceinline__ Runs wave_runs(int key) {
+    const int lane = lane_id();
+    Runs r;
+    const int next = __shfl_down(key, 1, kWave);
+    const int prev = __shfl_up(key, 1, kWave);
+    r.head = lane == kWave - 1 || next != key;
+    const bool starts = lane == 0 || prev != key;
+    // first lane of the run: the largest run start at or below this lane
+    int f = starts ? lane : 0;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(f, d, kWave);
+        if (lane >= d) f = max(f, y);
+    }
+    // longest run inside one 16-lane row, and whether any run crosses rows
+    const int row0 = lane & ~15;
+    int len = lane - max(f, row0) + 1;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) len = max(len, __shfl_xor(len, d, kWave));
+    int steps = 0;
+    while ((1 << steps) < len) ++steps;
+    r.nsteps = uniform(steps);
+    r.cross = uniform((int)__any((lane & 15) == 0 && f < lane)) != 0;
+    const int lr = lane & 15, row = lane >> 4;
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+        const int d = 1 << s2;
+        r.m[s2] = (lr >= d && lane - d >= f) ? 1.f : 0.f;
+    }
+    r.m[4] = ((row == 1 || row == 3) && 16 * row - 1 >= f) ? 1.f : 0.f;
+    r.m[5] = ((row == 2 || row == 3) && 31 >= f) ? 1.f : 0.f;
+    return r;
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float seg_step1(float x, float m) {
+    const float y = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWMASK, 0xF, true));
+    return __builtin_fmaf(y, m, x);
+}
+
+// The same segmented scan on one value.
+__device__ __forceinline__ float seg_scan1(float x, const Runs& r) {
+    if (r.nsteps > 0) x = seg_step1<0x111, 0xF>(x, r.m[0]);
+    if (r.nsteps > 1) x = seg_step1<0x112, 0xF>(x, r.m[1]);
+    if (r.nsteps > 2) x = seg_step1<0x114, 0xF>(x, r.m[2]);
+    if (r.nsteps > 3) x = seg_step1<0x118, 0xF>(x, r.m[3]);
+    if (r.cross) {
+        x = seg_step1<0x142, 0xA>(x, r.m[4]);
+        x = seg_step1<0x143, 0xC>(x, r.m[5]);
+    }
+    return x;
 }
 
 // Flush control row i (accumulator G) of the tile: dV partial and the rect
@@ -440,7 +503,7 @@ __device__ __forceinline__ void flush_row(const Surf& s, BwdState<QM>& st, const
         if (h > q) continue;
         const float c = st.act ? st.Nv[h] : 0.f;
         float4 x = make_float4(c * G.x, c * G.y, c * G.z, c * G.w);
-        seg_scan4<QM>(x, st);
+        seg_scan4(x, st);
         if (st.head) L->col[lane] = x;
         wave_lds_sync();
         {   // first 64 columns: head lane from the per-tile table
@@ -487,37 +550,13 @@ __device__ __forceinline__ void bwd_columns(const Surf& s, int q, int col0, floa
     st.ncols = ncols;
     st.nkeys = ncols - q;
     st.key_off = st.kb - kfirst;
-    const int nact = min(kWave, s.nv_s - col0);
-    const int kb_next = __shfl_down(st.kb, 1, kWave);
-    st.head = st.act && (lane == nact - 1 || kb_next != st.kb);
-    {   // first lane of the segment: the largest segment start at or below this lane
-        const int kb_prev = __shfl_up(st.kb, 1, kWave);
-        const bool starts = st.act && (lane == 0 || kb_prev != st.kb);
-        int f = starts ? lane : 0;
+    // runs of equal v-span; inactive lanes get keys of their own past the last span
+    const Runs rr = wave_runs(st.act ? st.kb : 0x40000000 + lane);
 #pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const int y = __shfl_up(f, d, kWave);
-            if (lane >= d) f = max(f, y);
-        }
-        const int seg_first = st.act ? f : kWave;  // inactive lanes never take
-        // longest run inside one 16-lane row, and whether any run crosses rows
-        const int row0 = lane & ~15;
-        int len = st.act ? lane - max(f, row0) + 1 : 1;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) len = max(len, __shfl_xor(len, d, kWave));
-        int steps = 0;
-        while ((1 << steps) < len) ++steps;
-        st.nsteps = uniform(steps);
-        st.cross = uniform((int)__any(st.act && (lane & 15) == 0 && seg_first < lane)) != 0;
-        const int lr = lane & 15, row = lane >> 4;
-#pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) {
-            const int d = 1 << s2;
-            st.m[s2] = (lr >= d && lane - d >= seg_first) ? 1.f : 0.f;
-        }
-        st.m[4] = ((row == 1 || row == 3) && 16 * row - 1 >= seg_first) ? 1.f : 0.f;
-        st.m[5] = ((row == 2 || row == 3) && 31 >= seg_first) ? 1.f : 0.f;
-    }
+    for (int s2 = 0; s2 < 6; ++s2) st.m[s2] = rr.m[s2];
+    st.nsteps = rr.nsteps;
+    st.cross = rr.cross;
+    st.head = st.act && rr.head;
     for (int o = lane; o < st.nkeys; o += kWave) L->head_of[o] = (short)-1;
     wave_lds_sync();
     if (st.head) L->head_of[st.key_off] = (short)lane;
@@ -705,8 +744,8 @@ constexpr int kFinW = 2 * kMaxDeg + 2;
 struct FinLds {
     float knots[kWG];
     int4 hdr[kFinMaxTiles];
-    float contrib[kWave * kFinW];  // per sample of the chunk, knot-window adjoints
-    int span[kWave];
+    float contrib[kWave * kFinW];  // per run head of the chunk, run sums of the knot-window adjoints
+    short head_of[kWG];            // span - first span of the chunk -> head lane, or -1
 };
 
 // Tiles of one surface in natural order (row blocks outer, 64-column blocks
@@ -717,11 +756,28 @@ struct TileRef {
     int alloc_rows;  // rows the slot was sized for (>= row1 - row0)
 };
 
+// Tile i of a surface whose equal-sized slots start at slot0 (pure
+// arithmetic: no table read on the finalize's dependent-load chains).
+__device__ __forceinline__ TileRef surface_tile(const char* slot0, size_t stride, int i, int ncb, int rows,
+                                                int nu_s) {
+    TileRef tr;
+    const int rb = i / ncb, cb = i - rb * ncb;
+    tr.slot = slot0 + (size_t)i * stride;
+    tr.col0 = cb * kWave;
+    tr.row0 = rb * rows;
+    tr.row1 = min(nu_s, tr.row0 + rows);
+    tr.alloc_rows = rows;
+    return tr;
+}
+
 // Knot gradient of one direction: for every sample x_a of the direction,
-// coef(a)[r] = dL/dN_{k_a-D+r}(x_a) is turned into per-knot adjoints by
-// basis_knot_adjoint; then each knot (one lane per knot) adds the adjoints of
-// the samples whose span window covers it, in sample order (spans are
-// non-decreasing, so those samples are contiguous), accumulating in FP64.
+// coef(a)[r] = dL/dN_{k_a-D+r}(x_a) is turned into per-knot adjoints
+// g_t(a) = d/dU_{k_a-D+t} by basis_knot_adjoint (t = 0..2D+1).  Samples come
+// 64 at a time; within a chunk, the samples of one span form a run of lanes
+// (spans are non-decreasing), so each g_t is first summed over its run by a
+// DPP segmented scan.  Knot kk then takes, for each t, the run sum of the
+// span kk + D - t (one LDS read through the run-head table), accumulating
+// in FP64 in a fixed order (chunks, then t).
 template <int D, class CoefAt>
 __device__ __forceinline__ void knot_gradient(const float* __restrict__ Ug, int nc, const float* __restrict__ xs,
                                               int ns, CoefAt coef_at, float* __restrict__ gout, FinLds* L) {
@@ -736,40 +792,64 @@ __device__ __forceinline__ void knot_gradient(const float* __restrict__ Ug, int 
     double acc[kWG / kWave];
 #pragma unroll
     for (int m = 0; m < kWG / kWave; ++m) acc[m] = 0.0;
-    for (int a0 = 0; a0 < ns; a0 += kWave) {
-        const int a = a0 + lane;
-        const int cnt = min(kWave, ns - a0);
-        int k = 0x7fffffff;
-        if (a < ns) {
-            const float x = clamp_param(U, D, n, xs[a]);
-            k = find_span(U, D, n, x);
+    for (int g0 = 0; g0 < ns; g0 += kWG) {
+        // the parameters of four chunks are fetched together, and each chunk's
+        // coefficients while the previous chunk is being worked on
+        float xv[kWG / kWave];
+#pragma unroll
+        for (int c = 0; c < kWG / kWave; ++c) xv[c] = xs[min(g0 + c * kWave + lane, ns - 1)];
+        float en[D + 1];
+        coef_at(min(g0 + lane, ns - 1), en);
+#pragma unroll
+        for (int c = 0; c < kWG / kWave; ++c) {
+            const int a0 = g0 + c * kWave;
+            if (a0 >= ns) break;
+            const int a = a0 + lane;
+            const int cnt = min(kWave, ns - a0);
+            const bool valid = a < ns;
             float e[D + 1];
-            coef_at(a, e);
+#pragma unroll
+            for (int r = 0; r <= D; ++r) e[r] = en[r];
+            if (c + 1 < kWG / kWave && a0 + kWave < ns) coef_at(min(a + kWave, ns - 1), en);
+            int k = 0;
             float g[W];
-            basis_knot_adjoint<D>(U, k, x, e, g);
 #pragma unroll
-            for (int t = 0; t < W; ++t) L->contrib[lane * W + t] = g[t];
-        }
-        L->span[lane] = k;
-        wave_lds_sync();
+            for (int t = 0; t < W; ++t) g[t] = 0.0f;
+            if (valid) {
+                const float x = clamp_param(U, D, n, xv[c]);
+                k = find_span(U, D, n, x);
+                basis_knot_adjoint<D>(U, k, x, e, g);
+            }
+            const int kfirst = bcast_lane(k, 0);
+            const int nkeys = bcast_lane(k, cnt - 1) - kfirst + 1;
+            // lanes past the last sample get keys of their own (runs of one, adding zeros)
+            const int key = valid ? k - kfirst : 0x40000000 + lane;
+            const Runs rr = wave_runs(key);
 #pragma unroll
-        for (int m = 0; m < kWG / kWave; ++m) {
-            const int kk = lane + m * kWave;
-            if (kk < nk) {
-                // first sample of the chunk whose span is >= kk - D - 1
-                int lo = 0, hi = cnt;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (L->span[mid] < kk - D - 1) lo = mid + 1; else hi = mid;
-                }
-                for (int r = lo; r < cnt; ++r) {
-                    const int sp = L->span[r];
-                    if (sp > kk + D) break;
-                    acc[m] += (double)L->contrib[r * W + (kk - (sp - D))];
+            for (int t = 0; t < W; ++t) g[t] = seg_scan1(g[t], rr);
+            for (int o = lane; o < nkeys; o += kWave) L->head_of[o] = (short)-1;
+            wave_lds_sync();
+            if (valid && rr.head) {
+                L->head_of[key] = (short)lane;
+#pragma unroll
+                for (int t = 0; t < W; ++t) L->contrib[lane * W + t] = g[t];
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int m = 0; m < kWG / kWave; ++m) {
+                if (m * kWave >= nk) break;
+                const int kk = lane + m * kWave;
+                if (kk < nk) {
+#pragma unroll
+                    for (int t = 0; t < W; ++t) {
+                        const int o = kk + D - t - kfirst;
+                        const int hl = (o >= 0 && o < nkeys) ? (int)L->head_of[o] : -1;
+                        if (hl >= 0) acc[m] += (double)L->contrib[hl * W + t];
+                    }
                 }
             }
+            wave_lds_sync();
         }
-        wave_lds_sync();
     }
 #pragma unroll
     for (int m = 0; m < kWG / kWave; ++m) {
@@ -785,7 +865,7 @@ constexpr int kFinChunk = kWave * kFinCp;  // control points per dP/dW part
 constexpr int kFinKU = 0, kFinKV = 1, kFinPW = 2;
 
 // Sum of the tile rectangles over this lane's control points of one chunk,
-// tiles in fixed order (each tile's kFinCp loads per lane in flight together).
+// tiles in fixed order, two tiles' loads in flight at a time.
 template <class TileAt>
 __device__ __forceinline__ void fin_pw_chunk(const Surf& s, int ntiles, TileAt tile_at, int chunk,
                                              float* __restrict__ gctrl, float* __restrict__ gw, unsigned mask,
@@ -806,18 +886,19 @@ __device__ __forceinline__ void fin_pw_chunk(const Surf& s, int ntiles, TileAt t
         ii[c] = ij / s.nv_c;
         jj[c] = ij - ii[c] * s.nv_c;
     }
-    auto add_tile = [&](int t) {
+    auto load_tile = [&](int t, float4 v[kFinCp]) {
         const char* slot = tile_at(t).slot;
         const int4 h = hdr_lds ? L->hdr[t] : *reinterpret_cast<const int4*>(slot);
         const float4* rect = reinterpret_cast<const float4*>(slot + 16);
         const int pitch = h.w - h.z + 1;
-        float4 v[kFinCp];
 #pragma unroll
         for (int c = 0; c < kFinCp; ++c) {
             const int ij = base + c * kWave + lane;
             const bool in = ij < ncp && ii[c] >= h.x && ii[c] <= h.y && jj[c] >= h.z && jj[c] <= h.w;
             v[c] = in ? rect[(size_t)(ii[c] - h.x) * pitch + (jj[c] - h.z)] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
+    };
+    auto add = [&](const float4 v[kFinCp]) {
 #pragma unroll
         for (int c = 0; c < kFinCp; ++c) {
             acc[c].x += v[c].x;
@@ -826,7 +907,20 @@ __device__ __forceinline__ void fin_pw_chunk(const Surf& s, int ntiles, TileAt t
             acc[c].w += v[c].w;
         }
     };
-    for (int t = 0; t < ntiles; ++t) add_tile(t);
+    // two tiles' loads in flight at a time; sums still in tile order
+    int t = 0;
+    for (; t + 1 < ntiles; t += 2) {
+        float4 va[kFinCp], vb[kFinCp];
+        load_tile(t, va);
+        load_tile(t + 1, vb);
+        add(va);
+        add(vb);
+    }
+    if (t < ntiles) {
+        float4 va[kFinCp];
+        load_tile(t, va);
+        add(va);
+    }
 #pragma unroll
     for (int c = 0; c < kFinCp; ++c) {
         const int ij = base + c * kWave + lane;

@@ -23,6 +23,7 @@ struct DevDesc {
     int tile_first, tile_count;  // backward tiles of this surface, natural order
     int rows;                    // rows per backward tile of this surface
     int pad;
+    long long slot0;             // byte offset of its first backward slot (the others follow, equal-sized)
 };
 
 // One tile of a ragged batch.
