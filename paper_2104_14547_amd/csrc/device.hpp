@@ -118,13 +118,17 @@ __device__ __forceinline__ int find_span(const float* __restrict__ U, int deg, i
 // alpha = (x-U_i)/(U_{i+d}-U_i), beta = (U_{i+d+1}-x)/(U_{i+d+1}-U_{i+1}).
 // The degree-0 indicator contributes no knot derivative (zero-bandwidth
 // limit of the paper's smoothing), so only the alpha/beta factors do.
-// FP32: every factor is a ratio of FP32 knot differences, so the result is
-// accurate to a few ulp per term.
+// FP32: every factor is a ratio of FP32 knot differences, taken as a product
+// with the hardware reciprocal refined by one Newton step, so each term is
+// accurate to a few ulp.
 template <int D>
 __device__ __forceinline__ void basis_knot_adjoint(const float* __restrict__ U, int k, float x,
                                                    const float e[D + 1], float gU[2 * D + 2]) {
-    // forward triangle T[d][idx] = N_{k-d+idx}^d
+    // forward triangle T[d][idx] = N_{k-d+idx}^d, with the reciprocals of the
+    // alpha / beta denominators kept for the reverse sweep (0 for an empty
+    // knot interval: the term is dropped)
     float T[D + 1][D + 1];
+    float ia[D + 1][D + 1], ib[D + 1][D + 1];
     T[0][0] = 1.0f;
 #pragma unroll
     for (int d = 1; d <= D; ++d) {
@@ -132,13 +136,20 @@ __device__ __forceinline__ void basis_knot_adjoint(const float* __restrict__ U, 
         for (int idx = 0; idx <= d; ++idx) {
             const int i = k - d + idx;
             float v = 0.0f;
+            ia[d][idx] = ib[d][idx] = 0.0f;
             if (idx >= 1) {
                 const float den = U[i + d] - U[i];
-                if (den != 0.0f) v += (x - U[i]) / den * T[d - 1][idx - 1];
+                if (den != 0.0f) {
+                    ia[d][idx] = recip(den);
+                    v += (x - U[i]) * ia[d][idx] * T[d - 1][idx - 1];
+                }
             }
             if (idx <= d - 1) {
                 const float den = U[i + d + 1] - U[i + 1];
-                if (den != 0.0f) v += (U[i + d + 1] - x) / den * T[d - 1][idx];
+                if (den != 0.0f) {
+                    ib[d][idx] = recip(den);
+                    v += (U[i + d + 1] - x) * ib[d][idx] * T[d - 1][idx];
+                }
             }
             T[d][idx] = v;
         }
@@ -159,28 +170,20 @@ __device__ __forceinline__ void basis_knot_adjoint(const float* __restrict__ U, 
             const int t = D - d + idx;  // window slot of U_i
             const float Ai = A[idx];
             if (idx >= 1) {
+                const float inv = ia[d][idx];
                 const float Ui = U[i], Uid = U[i + d];
-                const float den = Uid - Ui;
-                if (den != 0.0f) {
-                    const float Np = T[d - 1][idx - 1];
-                    const float inv = 1.0f / den;
-                    const float c = Ai * Np * inv * inv;
-                    An[idx - 1] += Ai * (x - Ui) * inv;
-                    gU[t] += c * (x - Uid);
-                    gU[t + d] -= c * (x - Ui);
-                }
+                const float c = Ai * T[d - 1][idx - 1] * inv * inv;
+                An[idx - 1] += Ai * (x - Ui) * inv;
+                gU[t] += c * (x - Uid);
+                gU[t + d] -= c * (x - Ui);
             }
             if (idx <= d - 1) {
+                const float inv = ib[d][idx];
                 const float Ui1 = U[i + 1], Uid1 = U[i + d + 1];
-                const float den = Uid1 - Ui1;
-                if (den != 0.0f) {
-                    const float Np = T[d - 1][idx];
-                    const float inv = 1.0f / den;
-                    const float c = Ai * Np * inv * inv;
-                    An[idx] += Ai * (Uid1 - x) * inv;
-                    gU[t + 1] += c * (Uid1 - x);
-                    gU[t + d + 1] += c * (x - Ui1);
-                }
+                const float c = Ai * T[d - 1][idx] * inv * inv;
+                An[idx] += Ai * (Uid1 - x) * inv;
+                gU[t + 1] += c * (Uid1 - x);
+                gU[t + d + 1] += c * (x - Ui1);
             }
         }
 #pragma unroll
