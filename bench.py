@@ -205,6 +205,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4096, help="surfaces timed on the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="default tiles instead of the autotuned ones")
     ap.add_argument("--served-requests", type=int, default=3000,
                     help="requests per arrival rate in the served leg (0: skip it)")
     ap.add_argument("--fit-steps", type=int, default=500, help="steps of the fitting leg (0: skip it)")
@@ -242,7 +243,12 @@ def main():
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     inputs = [T(getattr(batch, k)) for k in ("ctrl", "w", "ku", "kv", "us", "vs")]
     upstream = T(batch.upstream)
-    plan = nd.SurfaceBatch(batch.shapes, batch.offsets, device=0)
+    if args.no_autotune:
+        plan, tune = nd.SurfaceBatch(batch.shapes, batch.offsets, device=0), None
+    else:
+        t1 = time.perf_counter()
+        plan, tune = nd.api.autotune(batch.shapes, batch.offsets, inputs, upstream, device=0)
+        log(f"[bench] autotune {tune} ({time.perf_counter() - t1:.1f} s)")
     info = plan.info()
     pts = torch.empty(plan.n_pts_floats, dtype=torch.float32, device=dev)
     grads = tuple(torch.empty_like(x) for x in inputs[:4])
@@ -296,12 +302,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": batch.name, "surfaces": batch.n, "points": ab["points"],
                    "control_points": ab["control_points"], "degrees": "p,q in 1..5",
-                   "launches_per_step": 3},
+                   "launches_per_step": 3,
+                   "tiles": tune["chosen"] if tune else "default (16384 points)"},
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "kernels": kernels,
         "step_algorithmic_GBs": (ab["fwd"] + ab["bwd"] + ab["fin"]) / (ms_step * 1e-3) / 1e9,
     }
+    if tune:
+        result["autotune_ms"] = {d: {str(k): v for k, v in tune[d].items()} for d in ("fwd", "bwd")}
     if not args.no_parity:
         t1 = time.perf_counter()
         result["parity"] = parity_sample(batch, pts.cpu().numpy(), [g.cpu().numpy() for g in grads])

@@ -107,6 +107,13 @@ int nurbs_ctx_set_flags(nurbs_ctx *ctx, unsigned flags);
  * which knot gradients are the exact derivative of the piecewise-polynomial
  * basis, is supported; any other value returns NURBS_EUNSUPPORTED. */
 int nurbs_ctx_set_knot_sigma(nurbs_ctx *ctx, float sigma);
+/* Tiling of later calls on this context: the target number of sample points
+ * per forward / backward tile (a tile is one wave over <= 64 sample columns
+ * and as many rows as reach the target; 0 restores the default, 16384).
+ * Results stay bitwise reproducible for a given tiling; different tilings
+ * change the summation order of the backward within the tolerances.  An
+ * autotuner picks these per workload. */
+int nurbs_ctx_set_tiling(nurbs_ctx *ctx, int fwd_tile_points, int bwd_tile_points);
 const char *nurbs_status_string(int status);
 /* Text of the last error raised on this context (never NULL). */
 const char *nurbs_last_error(nurbs_ctx *ctx);

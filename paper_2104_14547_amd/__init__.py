@@ -18,6 +18,8 @@ def __getattr__(name):
     import importlib
     if name.startswith("__"):
         raise AttributeError(name)
+    if name in ("api", "fit", "serve", "workloads", "build"):
+        return importlib.import_module(__name__ + "." + name)
     api = importlib.import_module(__name__ + ".api")
     if hasattr(api, name):
         return getattr(api, name)

@@ -34,6 +34,7 @@ NURBS_MAX_DEGREE = 7
 # every symbol include/nurbsdiff.h declares
 EXPORTS = (
     "nurbs_ctx_create", "nurbs_ctx_destroy", "nurbs_ctx_set_flags", "nurbs_ctx_set_knot_sigma",
+    "nurbs_ctx_set_tiling",
     "nurbs_status_string", "nurbs_last_error", "nurbs_ctx_device_info",
     "nurbs_surface_ws_bytes", "nurbs_surface_fwd", "nurbs_surface_bwd",
     "nurbs_plan_create", "nurbs_plan_create_in", "nurbs_plan_destroy", "nurbs_plan_info", "nurbs_plan_fwd", "nurbs_plan_bwd",
@@ -61,6 +62,7 @@ _SIGS = {
     "nurbs_ctx_destroy": (_i, [_vp]),
     "nurbs_ctx_set_flags": (_i, [_vp, _u]),
     "nurbs_ctx_set_knot_sigma": (_i, [_vp, ctypes.c_float]),
+    "nurbs_ctx_set_tiling": (_i, [_vp, _i, _i]),
     "nurbs_status_string": (ctypes.c_char_p, [_i]),
     "nurbs_last_error": (ctypes.c_char_p, [_vp]),
     "nurbs_ctx_device_info": (_i, [_vp, _ip, _ip]),

@@ -73,6 +73,11 @@ class Context:
     def set_knot_sigma(self, sigma: float):
         _check(N.lib().nurbs_ctx_set_knot_sigma(self.handle, float(sigma)), self.handle)
 
+    def set_tiling(self, fwd_tile_points: int = 0, bwd_tile_points: int = 0):
+        """Target sample points per forward / backward tile of later calls (0: default)."""
+        _check(N.lib().nurbs_ctx_set_tiling(self.handle, int(fwd_tile_points), int(bwd_tile_points)), self.handle)
+        self.tiling = (int(fwd_tile_points) or 16384, int(bwd_tile_points) or 16384)
+
     def device_info(self):
         cus, wave = ctypes.c_int(), ctypes.c_int()
         _check(N.lib().nurbs_ctx_device_info(self.handle, ctypes.byref(cus), ctypes.byref(wave)), self.handle)
@@ -354,3 +359,54 @@ def basis(knots, p: int, x):
     _check(N.lib().nurbs_basis(_ptr(knots), knots.numel(), int(p), _ptr(x), x.numel(), _ptr(out),
                                _stream(x.device)))
     return out
+
+
+# --------------------------------------------------------------------------
+# tile autotuning
+# --------------------------------------------------------------------------
+
+TILE_CANDIDATES = (4096, 8192, 16384, 32768, 65536)
+
+
+def autotune(shapes, offsets, inputs, upstream, device: int | None = None, candidates=TILE_CANDIDATES,
+             reps: int = 5, validate: bool = False):
+    """Pick the forward and backward tile sizes for a ragged batch by timing.
+
+    Every candidate target (sample points per tile) is timed on the batch
+    itself -- the forward and the backward (with its finalize) separately,
+    ``reps`` calls each after a warm-up call, with HIP events on the plan's
+    stream -- and the fastest of each direction is kept.  Returns
+    ``(plan, report)``: a SurfaceBatch built with the chosen tiling (on a
+    context of its own) and the timings in ms per candidate."""
+    ctrl, w, ku, kv, us, vs = inputs
+    dev = ctrl.device
+    report = {"fwd": {}, "bwd": {}}
+    pts = None
+    grads = (torch.empty_like(ctrl), torch.empty_like(w), torch.empty_like(ku), torch.empty_like(kv))
+    for cand in candidates:
+        ctx = Context(device, validate=validate)
+        ctx.set_tiling(cand, cand)
+        plan = SurfaceBatch(shapes, offsets, device=device, validate=validate, ctx=ctx)
+        if pts is None:
+            pts = torch.empty(plan.n_pts_floats, dtype=torch.float32, device=dev)
+        plan.workspace()
+        plan.forward(ctrl, w, ku, kv, us, vs, out=pts)
+        plan.backward(ctrl, w, ku, kv, us, vs, upstream, out=grads)
+        torch.cuda.synchronize(dev)
+        plan.set_timing(reps)
+        for _ in range(reps):
+            plan.forward(ctrl, w, ku, kv, us, vs, out=pts)
+            plan.backward(ctrl, w, ku, kv, us, vs, upstream, out=grads)
+        torch.cuda.synchronize(dev)
+        f, b, z = plan.read_timing()
+        plan.set_timing(0)
+        report["fwd"][cand] = float(np.median(f))
+        report["bwd"][cand] = float(np.median(b + z))
+        plan.close()
+        del plan
+    best_f = min(report["fwd"], key=report["fwd"].get)
+    best_b = min(report["bwd"], key=report["bwd"].get)
+    ctx = Context(device, validate=validate)
+    ctx.set_tiling(best_f, best_b)
+    report["chosen"] = {"fwd_tile_points": best_f, "bwd_tile_points": best_b}
+    return SurfaceBatch(shapes, offsets, device=device, validate=validate, ctx=ctx), report

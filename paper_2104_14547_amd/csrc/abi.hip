@@ -22,6 +22,8 @@ struct nurbs_ctx {
     unsigned flags = 0;
     int num_cus = 0;
     int occ[2][2] = {{0, 0}, {0, 0}};  // persistent-kernel workgroups per CU: [class d5, d7][fwd, bwd]
+    int fwd_tile_pts = 16384;          // target points per forward / backward tile
+    int bwd_tile_pts = 16384;
     std::string err;
 };
 
@@ -99,8 +101,6 @@ int check_shape(nurbs_ctx* c, int p, int q, int nu_c, int nv_c, int nu_s, int nv
 // the same tiling -- and bitwise the same result -- alone, in a uniform
 // batch or in any ragged mix.  A tile is one wave64 over min(64, nv_s)
 // columns; the row count aims at a fixed number of points per tile.
-constexpr int kFwdTilePts = 16384;
-constexpr int kBwdTilePts = 16384;
 int tile_rows(int nu_s, int nv_s, int target_pts) {
     const int cols = std::max(1, std::min(kWave, nv_s));
     const int rows = std::max(1, target_pts / cols);
@@ -162,6 +162,17 @@ int nurbs_ctx_set_knot_sigma(nurbs_ctx* ctx, float sigma) {
     return NURBS_OK;
 }
 
+int nurbs_ctx_set_tiling(nurbs_ctx* ctx, int fwd_tile_points, int bwd_tile_points) {
+    if (!ctx) return fail(nullptr, NURBS_EINVAL, "ctx is NULL");
+    const int f = fwd_tile_points ? fwd_tile_points : 16384;
+    const int b = bwd_tile_points ? bwd_tile_points : 16384;
+    if (f < kWave || f > (1 << 22) || b < kWave || b > (1 << 22))
+        return fail(ctx, NURBS_EINVAL, "tile points must be in [64, 4194304] (or 0 for the default)");
+    ctx->fwd_tile_pts = f;
+    ctx->bwd_tile_pts = b;
+    return NURBS_OK;
+}
+
 const char* nurbs_last_error(nurbs_ctx* ctx) { return ctx ? ctx->err.c_str() : g_noctx_err.c_str(); }
 
 int nurbs_ctx_device_info(nurbs_ctx* ctx, int* num_cus, int* wave_size) {
@@ -186,8 +197,8 @@ UniformGeom uniform_geom(const nurbs_ctx* c, int B, int p, int q, int nu_c, int 
     UniformGeom g;
     g.ncb = (nv_s + kWave - 1) / kWave;
     const long long cols = (long long)B * g.ncb;
-    g.rows_f = tile_rows(nu_s, nv_s, kFwdTilePts);
-    g.rows_b = tile_rows(nu_s, nv_s, kBwdTilePts);
+    g.rows_f = tile_rows(nu_s, nv_s, c->fwd_tile_pts);
+    g.rows_b = tile_rows(nu_s, nv_s, c->bwd_tile_pts);
     g.nrb_f = (nu_s + g.rows_f - 1) / g.rows_f;
     g.nrb_b = (nu_s + g.rows_b - 1) / g.rows_b;
     g.tiles_f = cols * g.nrb_f;
@@ -398,8 +409,8 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
         x.us_off = d.us_off; x.vs_off = d.vs_off; x.pts_off = d.pts_off;
         x.pad = 0;
         const int ncb = (d.nv_s + kWave - 1) / kWave;
-        const int rf = tile_rows(d.nu_s, d.nv_s, kFwdTilePts);
-        const int rb = tile_rows(d.nu_s, d.nv_s, kBwdTilePts);
+        const int rf = tile_rows(d.nu_s, d.nv_s, ctx->fwd_tile_pts);
+        const int rb = tile_rows(d.nu_s, d.nv_s, ctx->bwd_tile_pts);
         x.rows = rb;
         x.tile_first = (int)bt.size();
         x.slot0 = (long long)(kWsHeader + slot_off);

@@ -395,3 +395,35 @@ def test_full_size_uneven_batch_sampled():
     check_points(sub, got_pts, S_or)
     check_grads(sub, got_g, G_or)
     assert np.isfinite(pts).all()
+
+
+# --------------------------------------------------------------------------
+# tile autotuning
+# --------------------------------------------------------------------------
+
+def test_autotuned_plan_parity_and_tiling_knob():
+    from paper_2104_14547_amd import api
+    b = uneven_subset().subset(range(20))
+    args = [T(getattr(b, k)) for k in ("ctrl", "w", "ku", "kv", "us", "vs")]
+    up = T(b.upstream)
+    plan, report = api.autotune(b.shapes, b.offsets, args, up, device=0, candidates=(1024, 8192, 65536), reps=2)
+    assert report["chosen"]["fwd_tile_points"] in (1024, 8192, 65536)
+    pts = plan.forward(*args)
+    grads = plan.backward(*args, up)
+    S_or, G_or = oracle_both(b, b.upstream)
+    check_points(b, H(pts), S_or)
+    check_grads(b, [H(g) for g in grads], G_or)
+    # every tiling stays within tolerance, and each is deterministic
+    for tp in (256, 4096):
+        ctx = api.Context(0)
+        ctx.set_tiling(tp, tp)
+        sb = nd.SurfaceBatch(b.shapes, b.offsets, device=0, ctx=ctx)
+        p1 = H(sb.forward(*args))
+        g1 = [H(g) for g in sb.backward(*args, up)]
+        p2 = H(sb.forward(*args))
+        g2 = [H(g) for g in sb.backward(*args, up)]
+        assert np.array_equal(p1, p2) and all(np.array_equal(x, y) for x, y in zip(g1, g2))
+        check_points(b, p1, S_or)
+        check_grads(b, g1, G_or)
+    with pytest.raises(nd.NurbsError):
+        api.Context(0).set_tiling(8, 8)
