@@ -68,6 +68,17 @@ __device__ __forceinline__ float recip(float x) {
     return __builtin_fmaf(r, e, r);
 }
 
+// 1/x from the hardware reciprocal alone (1 ulp): the per-point rational
+// divide, whose result is compared at 1e-5 of the surface's extent.
+__device__ __forceinline__ float recip_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// q = floor(n / d) for 0 <= n < 2^16 and 1 <= d < 2^16, through the FP32
+// reciprocal: the quotient's fractional part is at least 1/d away from the
+// next integer, far above the rounding of the product.
+__device__ __forceinline__ int small_div(int n, int d) {
+    return (int)(((float)n + 0.5f) * __builtin_amdgcn_rcpf((float)d));
+}
+
 // DPP lane moves (gfx9 encodings): quad_perm [1,0,3,2] = 0xB1,
 // quad_perm [2,3,0,1] = 0x4E, row_half_mirror = 0x141, row_mirror = 0x140.
 template <int CTRL>
@@ -235,7 +246,8 @@ __device__ __forceinline__ float4 row_contract(const Surf& s, int i, int jb, con
 // triangular Cox-de Boor scheme with left/right knot distances.  Every
 // denominator is a knot difference that contains [U_k, U_{k+1}], so it is
 // positive on a non-empty span.  FP32: the differences of FP32 inputs carry
-// one rounding each, so the values are accurate to a few ulp per degree.
+// one rounding each and the divides are reciprocal products, so the values
+// are accurate to a few ulp per degree.
 template <int D>
 __device__ __forceinline__ void basis_f32(const float* __restrict__ U, int k, float x, float N[D + 1]) {
     float left[D + 1], right[D + 1];
@@ -247,7 +259,7 @@ __device__ __forceinline__ void basis_f32(const float* __restrict__ U, int k, fl
         float saved = 0.0f;
 #pragma unroll
         for (int r = 0; r < j; ++r) {
-            const float tmp = N[r] / (right[r + 1] + left[j - r]);
+            const float tmp = N[r] * recip(right[r + 1] + left[j - r]);
             N[r] = saved + right[r + 1] * tmp;
             saved = left[j - r] * tmp;
         }

@@ -148,7 +148,7 @@ __device__ __forceinline__ void stage_block(const Surf& s, Block& bk, int lo) {
         for (int m = 0; m < kRound; ++m) {
             const int e = lane + (m0 + m) * kWave;
             if (e < n) {
-                const int r = e / bk.ncols, c = e - r * bk.ncols;
+                const int r = small_div(e, bk.ncols), c = e - r * bk.ncols;
                 const int ij = (lo + r) * s.nv_c + bk.j0 + c;
                 const float* cp = s.ctrl + 3 * ij;
                 raw[m] = make_float4(cp[0], cp[1], cp[2], s.w[ij]);
@@ -288,7 +288,7 @@ __device__ __forceinline__ void fwd_rows(const Surf& s, Block& bk, const float N
             float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
             for (int r = 0; r <= P; ++r) acc = fma4(bcast_lane(Nu_l[r], t), R[r], acc);
-            const float rw = recip(acc.w);
+            const float rw = recip_fast(acc.w);
             if (act) {
                 orow[0] = acc.x * rw;
                 orow[1] = acc.y * rw;
@@ -661,7 +661,7 @@ __device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, B
             float4 sp = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
             for (int r = 0; r <= P; ++r) sp = fma4(Nu[r], R[r], sp);
-            const float rw = recip(sp.w);
+            const float rw = recip_fast(sp.w);
             const float cx = g.x * rw, cy = g.y * rw, cz = g.z * rw;
             const float cw = -(cx * sp.x + cy * sp.y + cz * sp.z) * rw;
             const float4 hv = make_float4(cx, cy, cz, cw);
