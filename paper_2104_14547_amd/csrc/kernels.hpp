@@ -108,10 +108,10 @@ __device__ __forceinline__ void validate_surface(const Surf& s, int P, int Q, in
 // its loads in flight at once (one memory latency) and replaced only when
 // the u-window leaves it, so the row loops below carry no pending loads.
 // --------------------------------------------------------------------------
-constexpr int kBlkCap = 384;                 // float4 entries per wave (6 KiB)
+constexpr int kBlkCap = 320;                 // float4 entries per wave (5 KiB)
 constexpr int kBlkPerLane = kBlkCap / kWave;  // entries each lane loads
-constexpr int kEBatch = 16;                   // rows per batched reduction of dL/dN(u)
-constexpr int kGRows = 2;                     // rows of dL/dS staged per batch
+constexpr int kEBatch = 8;                    // rows per batched reduction of dL/dN(u)
+constexpr int kGRows = 1;                     // rows of dL/dS staged per batch
 
 struct Block {
     float4* base;  // LDS, [rows][ncols]
@@ -937,7 +937,7 @@ __device__ __forceinline__ void fin_pw_chunk(const Surf& s, int ntiles, TileAt t
 }
 
 // dL/dU: e(a) = sum over the column blocks of a's row block.
-template <int P, int Q, class TileAt>
+template <int P, class TileAt>
 __device__ __forceinline__ void fin_knots_u(const Surf& s, int ntiles, TileAt tile_at, float* __restrict__ gku,
                                             FinLds* L) {
     const size_t rect_bytes = 16 * (size_t)s.nu_c * s.nv_c;
@@ -958,10 +958,11 @@ __device__ __forceinline__ void fin_knots_u(const Surf& s, int ntiles, TileAt ti
     knot_gradient<P>(s.ku, s.nu_c, s.us, s.nu_s, coef, gku, L);
 }
 
-// dL/dV: f(b) = sum over the row blocks of b's column block.
-template <int P, int Q, class TileAt>
-__device__ __forceinline__ void fin_knots_v(const Surf& s, int ntiles, TileAt tile_at, float* __restrict__ gkv,
-                                            FinLds* L) {
+// dL/dV: f(b) = sum over the row blocks of b's column block (p, the degree
+// in u, only places f inside the slot).
+template <int Q, class TileAt>
+__device__ __forceinline__ void fin_knots_v(const Surf& s, int ntiles, TileAt tile_at, int p,
+                                            float* __restrict__ gkv, FinLds* L) {
     const size_t rect_bytes = 16 * (size_t)s.nu_c * s.nv_c;
     const int ncb = (s.nv_s + kWave - 1) / kWave;
     const int nrb = ncb > 0 ? ntiles / ncb : 0;
@@ -972,7 +973,7 @@ __device__ __forceinline__ void fin_knots_v(const Surf& s, int ntiles, TileAt ti
         for (int rb = 0; rb < nrb; ++rb) {
             const TileRef tr = tile_at(rb * ncb + cb);
             const float* fv = reinterpret_cast<const float*>(
-                tr.slot + 16 + rect_bytes + align16(sizeof(float) * (size_t)tr.alloc_rows * (P + 1)));
+                tr.slot + 16 + rect_bytes + align16(sizeof(float) * (size_t)tr.alloc_rows * (p + 1)));
 #pragma unroll
             for (int h = 0; h <= Q; ++h) f[h] += fv[(b - tr.col0) * (Q + 1) + h];
         }
@@ -980,18 +981,52 @@ __device__ __forceinline__ void fin_knots_v(const Surf& s, int ntiles, TileAt ti
     knot_gradient<Q>(s.kv, s.nv_c, s.vs, s.nv_s, coef, gkv, L);
 }
 
-// One finalize part (see kFinPW / kFinKU / kFinKV).
-template <int P, int Q, class TileAt>
-__device__ __forceinline__ void finalize_part(const Surf& s, int ntiles, TileAt tile_at, int part,
+// One finalize part (see kFinPW / kFinKU / kFinKV); the knot parts are
+// compiled per degree of their own direction only.
+template <int DM, class TileAt>
+__device__ __forceinline__ void finalize_part(const Surf& s, int ntiles, TileAt tile_at, int p, int q, int part,
                                               float* __restrict__ gctrl, float* __restrict__ gw,
                                               float* __restrict__ gku, float* __restrict__ gkv, unsigned mask,
                                               FinLds* L) {
     if (part >= kFinPW) {
         if (mask & 3u) fin_pw_chunk(s, ntiles, tile_at, part - kFinPW, gctrl, gw, mask, L);
     } else if (part == kFinKU) {
-        if (mask & 4u) fin_knots_u<P, Q>(s, ntiles, tile_at, gku, L);
+        if (!(mask & 4u)) return;
+        switch (p) {
+#define ND_KU(D) \
+    case D:      \
+        if constexpr (D <= DM) fin_knots_u<D>(s, ntiles, tile_at, gku, L); \
+        break;
+            ND_KU(1) ND_KU(2) ND_KU(3) ND_KU(4) ND_KU(5) ND_KU(6) ND_KU(7)
+#undef ND_KU
+            default: break;
+        }
     } else {
-        if (mask & 8u) fin_knots_v<P, Q>(s, ntiles, tile_at, gkv, L);
+        if (!(mask & 8u)) return;
+        switch (q) {
+#define ND_KV(D) \
+    case D:      \
+        if constexpr (D <= DM) fin_knots_v<D>(s, ntiles, tile_at, p, gkv, L); \
+        break;
+            ND_KV(1) ND_KV(2) ND_KV(3) ND_KV(4) ND_KV(5) ND_KV(6) ND_KV(7)
+#undef ND_KV
+            default: break;
+        }
+    }
+}
+
+// The same with both degrees known at compile time (uniform batches).
+template <int P, int Q, class TileAt>
+__device__ __forceinline__ void finalize_part_pq(const Surf& s, int ntiles, TileAt tile_at, int part,
+                                                 float* __restrict__ gctrl, float* __restrict__ gw,
+                                                 float* __restrict__ gku, float* __restrict__ gkv, unsigned mask,
+                                                 FinLds* L) {
+    if (part >= kFinPW) {
+        if (mask & 3u) fin_pw_chunk(s, ntiles, tile_at, part - kFinPW, gctrl, gw, mask, L);
+    } else if (part == kFinKU) {
+        if (mask & 4u) fin_knots_u<P>(s, ntiles, tile_at, gku, L);
+    } else {
+        if (mask & 8u) fin_knots_v<Q>(s, ntiles, tile_at, P, gkv, L);
     }
 }
 
@@ -1007,7 +1042,7 @@ __device__ __forceinline__ void finalize_surface(const Surf& s, int ntiles, Tile
                                                  float* __restrict__ gkv, unsigned mask, FinLds* L) {
     const int np = fin_parts(s.nu_c, s.nv_c);
     for (int part = 0; part < np; ++part) {
-        finalize_part<P, Q>(s, ntiles, tile_at, part, gctrl, gw, gku, gkv, mask, L);
+        finalize_part_pq<P, Q>(s, ntiles, tile_at, part, gctrl, gw, gku, gkv, mask, L);
         wave_lds_sync();
     }
 }
