@@ -206,6 +206,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="default tiles instead of the autotuned ones")
+    ap.add_argument("--tiles", default="", metavar="FWD,BWD",
+                    help="fixed sample points per forward,backward tile (skips the autotuner)")
     ap.add_argument("--served-requests", type=int, default=3000,
                     help="requests per arrival rate in the served leg (0: skip it)")
     ap.add_argument("--fit-steps", type=int, default=500, help="steps of the fitting leg (0: skip it)")
@@ -243,7 +245,13 @@ def main():
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     inputs = [T(getattr(batch, k)) for k in ("ctrl", "w", "ku", "kv", "us", "vs")]
     upstream = T(batch.upstream)
-    if args.no_autotune:
+    if args.tiles:
+        tf, tb = (int(x) for x in args.tiles.split(","))
+        ctx = nd.api.Context(0)
+        ctx.set_tiling(tf, tb)
+        plan = nd.SurfaceBatch(batch.shapes, batch.offsets, device=0, ctx=ctx)
+        tune = {"chosen": {"fwd_tile_points": tf, "bwd_tile_points": tb}, "fixed": True}
+    elif args.no_autotune:
         plan, tune = nd.SurfaceBatch(batch.shapes, batch.offsets, device=0), None
     else:
         t1 = time.perf_counter()
@@ -309,7 +317,7 @@ def main():
         "kernels": kernels,
         "step_algorithmic_GBs": (ab["fwd"] + ab["bwd"] + ab["fin"]) / (ms_step * 1e-3) / 1e9,
     }
-    if tune:
+    if tune and not tune.get("fixed"):
         result["autotune_ms"] = {d: {str(k): v for k, v in tune[d].items()} for d in ("fwd", "bwd")}
     if not args.no_parity:
         t1 = time.perf_counter()
