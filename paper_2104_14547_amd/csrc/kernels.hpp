@@ -285,6 +285,27 @@ __device__ __forceinline__ void fwd_rows(const Surf& s, Block& bk, const float N
                     for (int r = 0; r <= P; ++r) R[r] = blk_contract<QM, BLK>(s, bk, ka - P + r, jb, Nv, q);
                 }
             }
+            if (t + 1 < nr && bcast_lane(ka_l, t + 1) == ka) {
+                // two rows on the same window: their independent chains overlap
+                float4 acc = make_float4(0.f, 0.f, 0.f, 0.f), acc2 = acc;
+#pragma unroll
+                for (int r = 0; r <= P; ++r) {
+                    acc = fma4(bcast_lane(Nu_l[r], t), R[r], acc);
+                    acc2 = fma4(bcast_lane(Nu_l[r], t + 1), R[r], acc2);
+                }
+                const float rw = recip_fast(acc.w), rw2 = recip_fast(acc2.w);
+                if (act) {
+                    orow[0] = acc.x * rw;
+                    orow[1] = acc.y * rw;
+                    orow[2] = acc.z * rw;
+                    orow[ostride + 0] = acc2.x * rw2;
+                    orow[ostride + 1] = acc2.y * rw2;
+                    orow[ostride + 2] = acc2.z * rw2;
+                }
+                orow += 2 * ostride;
+                ++t;
+                continue;
+            }
             float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
             for (int r = 0; r <= P; ++r) acc = fma4(bcast_lane(Nu_l[r], t), R[r], acc);
