@@ -111,7 +111,6 @@ __device__ __forceinline__ void validate_surface(const Surf& s, int P, int Q, in
 constexpr int kBlkCap = 320;                 // float4 entries per wave (5 KiB)
 constexpr int kBlkPerLane = kBlkCap / kWave;  // entries each lane loads
 constexpr int kEBatch = 8;                    // rows per batched reduction of dL/dN(u)
-constexpr int kGRows = 1;                     // rows of dL/dS staged per batch
 
 struct Block {
     float4* base;  // LDS, [rows][ncols]
@@ -371,7 +370,6 @@ struct BwdLdsT {
     float4 blk[kBlkCap];
     float knots[2][kWG];
     float4 col[kWave];                      // run sums of one h, [head lane]
-    float3 g[kGRows][kWave];                // staged dL/dS rows
     short head_of[kWG];                     // key offset -> head lane, or -1
     float ebuf[kEBatch * 4 * (PM + 1)];     // 16-lane partials of dL/dNu
 };
@@ -381,7 +379,6 @@ struct BwdLds {
     float4* blk;
     float* knots[2];
     float4* col;
-    float3* g;
     short* head_of;
     float* ebuf;
 };
@@ -393,42 +390,42 @@ __device__ __forceinline__ BwdLds bwd_lds(BwdLdsT<PM, QM>* t) {
     l.knots[0] = t->knots[0];
     l.knots[1] = t->knots[1];
     l.col = t->col;
-    l.g = &t->g[0][0];
     l.head_of = t->head_of;
     l.ebuf = t->ebuf;
     return l;
 }
 
-// One step of a segmented inclusive scan with DPP on the four components
-// at once (independent moves, so their latencies overlap):
-// x += m * x[source lane].
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ void seg_step4(float4& x, float m) {
-    auto mv = [](float v) {
-        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, true));
-    };
-    const float yx = mv(x.x), yy = mv(x.y), yz = mv(x.z), yw = mv(x.w);
-    x.x = __builtin_fmaf(yx, m, x.x);
-    x.y = __builtin_fmaf(yy, m, x.y);
-    x.z = __builtin_fmaf(yz, m, x.z);
-    x.w = __builtin_fmaf(yw, m, x.w);
-}
+// One step of a segmented inclusive scan on the four components:
+// x += m * x[source lane], as one v_fmac_f32 per component that reads x
+// through DPP (the compiler emits a separate v_mov_b32_dpp for this form).
+// s_nop 1 gives the two wait states a DPP read needs after the last VALU
+// write of its register; inside the block each component was written four
+// instructions before it is read.
+#define ND_SEG_STEP4(x, m, DPP)                                 \
+    asm volatile("s_nop 1\n\t"                                 \
+                 "v_fmac_f32_dpp %0, %0, %4 " DPP "\n\t"        \
+                 "v_fmac_f32_dpp %1, %1, %4 " DPP "\n\t"        \
+                 "v_fmac_f32_dpp %2, %2, %4 " DPP "\n\t"        \
+                 "v_fmac_f32_dpp %3, %3, %4 " DPP                \
+                 : "+v"(x.x), "+v"(x.y), "+v"(x.z), "+v"(x.w)    \
+                 : "v"(m))
 
 // Segmented inclusive scan over the wave (segments are runs of equal
 // v-span): in-row Hillis-Steele steps (row_shr 1, 2, 4, 8), then the
 // row_bcast 15 / 31 steps that carry runs across 16-lane rows.  After it,
 // the last lane of each run holds the run's sum.  The step count and the
 // cross-row flag are wave-uniform, so the steps are taken or skipped by
-// scalar branches.  Fixed order: deterministic.
+// scalar branches.  Lanes without a source lane (bound_ctrl) or in rows the
+// step leaves out (row_mask) keep x.  Fixed order: deterministic.
 template <class S>
 __device__ __forceinline__ void seg_scan4(float4& x, const S& st) {
-    if (st.nsteps > 0) seg_step4<0x111, 0xF>(x, st.m[0]);
-    if (st.nsteps > 1) seg_step4<0x112, 0xF>(x, st.m[1]);
-    if (st.nsteps > 2) seg_step4<0x114, 0xF>(x, st.m[2]);
-    if (st.nsteps > 3) seg_step4<0x118, 0xF>(x, st.m[3]);
+    if (st.nsteps > 0) ND_SEG_STEP4(x, st.m[0], "row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    if (st.nsteps > 1) ND_SEG_STEP4(x, st.m[1], "row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    if (st.nsteps > 2) ND_SEG_STEP4(x, st.m[2], "row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    if (st.nsteps > 3) ND_SEG_STEP4(x, st.m[3], "row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:1");
     if (st.cross) {
-        seg_step4<0x142, 0xA>(x, st.m[4]);
-        seg_step4<0x143, 0xC>(x, st.m[5]);
+        ND_SEG_STEP4(x, st.m[4], "row_bcast:15 row_mask:0xa bank_mask:0xf");
+        ND_SEG_STEP4(x, st.m[5], "row_bcast:31 row_mask:0xc bank_mask:0xf");
     }
 }
 
@@ -476,23 +473,22 @@ __device__ __forceinline__ Runs wave_runs(int key) {
     return r;
 }
 
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ float seg_step1(float x, float m) {
-    const float y = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWMASK, 0xF, true));
-    return __builtin_fmaf(y, m, x);
-}
-
-// The same segmented scan on one value.
-__device__ __forceinline__ float seg_scan1(float x, const Runs& r) {
-    if (r.nsteps > 0) x = seg_step1<0x111, 0xF>(x, r.m[0]);
-    if (r.nsteps > 1) x = seg_step1<0x112, 0xF>(x, r.m[1]);
-    if (r.nsteps > 2) x = seg_step1<0x114, 0xF>(x, r.m[2]);
-    if (r.nsteps > 3) x = seg_step1<0x118, 0xF>(x, r.m[3]);
+// The same segmented scan on two values.
+#define ND_SEG_STEP2(x, y, m, DPP)                              \
+    asm volatile("s_nop 1\n\t"                                 \
+                 "v_fmac_f32_dpp %0, %0, %2 " DPP "\n\t"        \
+                 "v_fmac_f32_dpp %1, %1, %2 " DPP                \
+                 : "+v"(x), "+v"(y)                              \
+                 : "v"(m))
+__device__ __forceinline__ void seg_scan2(float& x, float& y, const Runs& r) {
+    if (r.nsteps > 0) ND_SEG_STEP2(x, y, r.m[0], "row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    if (r.nsteps > 1) ND_SEG_STEP2(x, y, r.m[1], "row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    if (r.nsteps > 2) ND_SEG_STEP2(x, y, r.m[2], "row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:1");
+    if (r.nsteps > 3) ND_SEG_STEP2(x, y, r.m[3], "row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:1");
     if (r.cross) {
-        x = seg_step1<0x142, 0xA>(x, r.m[4]);
-        x = seg_step1<0x143, 0xC>(x, r.m[5]);
+        ND_SEG_STEP2(x, y, r.m[4], "row_bcast:15 row_mask:0xa bank_mask:0xf");
+        ND_SEG_STEP2(x, y, r.m[5], "row_bcast:31 row_mask:0xc bank_mask:0xf");
     }
-    return x;
 }
 
 // Flush control row i (accumulator G) of the tile: dV partial and the rect
@@ -609,23 +605,14 @@ __device__ __forceinline__ void flush_e(BwdLds* L, int nb, float* __restrict__ e
     wave_lds_sync();
 }
 
-// Stage dL/dS of rows [a, a + n) (n <= kGRows) of this lane's column:
-// all loads in flight together, then into LDS.
-__device__ __forceinline__ void stage_g(const float* __restrict__ gpts, int a, int n, int nv_s, int b, bool act,
-                                        BwdLds* L) {
-    const int lane = lane_opaque();
-    float3 v[kGRows];
-    const float* gp = gpts + 3 * ((size_t)a * nv_s + b);
-#pragma unroll
-    for (int j = 0; j < kGRows; ++j) {
-        v[j] = make_float3(0.f, 0.f, 0.f);
-        if (act && j < n) v[j] = make_float3(gp[0], gp[1], gp[2]);
-        gp += 3 * (size_t)nv_s;
+// dL/dS of row a for this lane's column (zero on inactive lanes)
+__device__ __forceinline__ float3 load_g(const float* __restrict__ gpts, int a, int nv_s, int b, bool act) {
+    float3 v = make_float3(0.f, 0.f, 0.f);
+    if (act) {
+        const float* gp = gpts + 3 * ((size_t)a * nv_s + b);
+        v = make_float3(gp[0], gp[1], gp[2]);
     }
-    wave_lds_sync();
-#pragma unroll
-    for (int j = 0; j < kGRows; ++j) L->g[j * kWave + lane] = v[j];
-    wave_lds_sync();
+    return v;
 }
 
 template <int P, int QM, bool BLK>
@@ -640,6 +627,8 @@ __device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, B
     const int b = col0 + lane;
     float4 R[P + 1], G[P + 1];
     int cur = -1, i0 = 0;
+    // dL/dS is loaded one row ahead of its use, straight into registers
+    float3 gn = load_g(gpts, row0, s.nv_s, b, st.act);
     for (int a0 = row0; a0 < row1; a0 += kWave) {
         const int nr = min(kWave, row1 - a0);
         float Nu_l[P + 1];
@@ -647,7 +636,8 @@ __device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, B
         const int ka_l = sample_basis<P>(s.ku, s.nu_c, ua, Nu_l);
         int eb = 0;  // rows in the current dL/dNu batch
         for (int t = 0; t < nr; ++t) {
-            if ((t & (kGRows - 1)) == 0) stage_g(gpts, a0 + t, min(kGRows, nr - t), s.nv_s, b, st.act, L);
+            const float3 g = gn;
+            if (a0 + t + 1 < row1) gn = load_g(gpts, a0 + t + 1, s.nv_s, b, st.act);
             const int ka = bcast_lane(ka_l, t);
             if (cur < 0) {
                 cur = ka;
@@ -674,7 +664,6 @@ __device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, B
                     R[P] = blk_contract<QM, BLK>(s, bk, cur, st.jb, st.Nv, q);
                 }
             }
-            const float3 g = L->g[(t & (kGRows - 1)) * kWave + lane];
             float Nu[P + 1];
 #pragma unroll
             for (int r = 0; r <= P; ++r) Nu[r] = bcast_lane(Nu_l[r], t);
@@ -846,8 +835,17 @@ __device__ __forceinline__ void knot_gradient(const float* __restrict__ Ug, int 
             // lanes past the last sample get keys of their own (runs of one, adding zeros)
             const int key = valid ? k - kfirst : 0x40000000 + lane;
             const Runs rr = wave_runs(key);
+            // W = 2D is even: four values per scan while they last, then two
 #pragma unroll
-            for (int t = 0; t < W; ++t) g[t] = seg_scan1(g[t], rr);
+            for (int t = 0; t + 3 < W; t += 4) {
+                float4 x = make_float4(g[t], g[t + 1], g[t + 2], g[t + 3]);
+                seg_scan4(x, rr);
+                g[t] = x.x;
+                g[t + 1] = x.y;
+                g[t + 2] = x.z;
+                g[t + 3] = x.w;
+            }
+            if constexpr (W % 4 != 0) seg_scan2(g[W - 2], g[W - 1], rr);
             for (int o = lane; o < nkeys; o += kWave) L->head_of[o] = (short)-1;
             wave_lds_sync();
             if (valid && rr.head) {
