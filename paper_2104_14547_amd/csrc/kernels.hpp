@@ -678,10 +678,14 @@ __device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, B
 #pragma unroll
             for (int r = 0; r <= P; ++r) G[r] = fma4(Nu[r], hv, G[r]);
             if (want_ku) {
+                float e[P + 1];
 #pragma unroll
-                for (int r = 0; r <= P; ++r) {
-                    const float e = row16_sum(dot4(R[r], hv));
-                    if ((lane & 15) == 0) L->ebuf[(eb * 4 + (lane >> 4)) * (P + 1) + r] = e;
+                for (int r = 0; r <= P; ++r) e[r] = dot4(R[r], hv);
+                row16_sum_n(e);
+                if ((lane & 15) == 0) {
+                    float* dst = L->ebuf + (eb * 4 + (lane >> 4)) * (P + 1);
+#pragma unroll
+                    for (int r = 0; r <= P; ++r) dst[r] = e[r];
                 }
                 if (++eb == kEBatch) {
                     flush_e<P>(L, eb, out.e + (size_t)(a0 + t + 1 - eb - row0) * (P + 1));
