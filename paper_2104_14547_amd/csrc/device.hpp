@@ -79,29 +79,15 @@ __device__ __forceinline__ int small_div(int n, int d) {
     return (int)(((float)n + 0.5f) * __builtin_amdgcn_rcpf((float)d));
 }
 
-// DPP lane moves (gfx9 encodings): quad_perm [1,0,3,2] = 0xB1,
-// quad_perm [2,3,0,1] = 0x4E, row_half_mirror = 0x141, row_mirror = 0x140.
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
-}
-
-// Sum over each 16-lane DPP row; every lane of the row gets the row's sum.
-// Fixed pairing order, so the result is bitwise reproducible.
-__device__ __forceinline__ float row16_sum(float x) {
-    x += dpp_mov<0xB1>(x);
-    x += dpp_mov<0x4E>(x);
-    x += dpp_mov<0x141>(x);
-    x += dpp_mov<0x140>(x);
-    return x;
-}
-
-// row16_sum on N values at once.  Each butterfly step is one v_add_f32
+// Sums over each 16-lane DPP row, every lane of the row getting its row's
+// sum, for N values at once.  Four butterfly steps in a fixed order
+// (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror),
+// so the result is bitwise reproducible.  Each step is one v_add_f32
 // reading its other operand through DPP; the values go through the steps
 // interleaved, four (or two, or one) to an asm block, so a value's next DPP
 // read comes two instructions or more after its write (s_nop fills in for
 // fewer than three values); each block opens with s_nop 1 for the writes
-// before it.  Same pairing order as row16_sum, so the same bits.
+// before it.
 __device__ __forceinline__ void row16_sum4(float& a, float& b, float& c, float& d) {
     asm volatile("s_nop 1\n\t"
                  "v_add_f32_dpp %0, %0, %0 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
@@ -154,12 +140,6 @@ __device__ __forceinline__ void row16_sum_n(float (&x)[N]) {
     for (int i = 0; i + 3 < N; i += 4) row16_sum4(x[i], x[i + 1], x[i + 2], x[i + 3]);
     if constexpr (N % 4 >= 2) row16_sum2(x[N - (N % 4)], x[N - (N % 4) + 1]);
     if constexpr (N % 2 == 1) row16_sum1(x[N - 1]);
-}
-
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-    for (int m = 1; m < kWave; m <<= 1) x += __shfl_xor(x, m, kWave);
-    return x;
 }
 
 // ---------------------------------------------------------------------------
