@@ -752,7 +752,7 @@ __device__ __forceinline__ void bwd_tile(const Surf& sg, int q, int col0, int ro
 // finalize: one wave per surface (kWavesPerWG surfaces per workgroup)
 // --------------------------------------------------------------------------
 constexpr int kFinMaxTiles = 64;  // tile headers staged in LDS (more: read from global)
-constexpr int kFinCp = 8;         // control points per lane per pass
+constexpr int kFinCp = 4;         // control points per lane per pass (registers for six waves/SIMD)
 constexpr int kFinW = 2 * kMaxDeg + 2;
 
 struct FinLds {
