@@ -23,9 +23,11 @@
  *    allocates on a hot-path call (plans allocate their tables once, at
  *    creation).  Outputs are fully overwritten, never accumulated.
  *  - Degrees: 1 <= p, q <= NURBS_MAX_DEGREE; control sides nu_c >= p+1,
- *    nv_c >= q+1.  Knot vectors have nu_c+p+1 (nv_c+q+1) entries, are
+ *    nv_c >= q+1.  Knot vectors have nu_c+p+1 (nv_c+q+1) entries, at most
+ *    NURBS_MAX_KNOTS each (so nu_c <= NURBS_MAX_KNOTS-p-1), are
  *    non-decreasing, and satisfy U_p < U_{p+1} and U_{nu_c-1} < U_{nu_c}.
- *    Weights are > 0.
+ *    nu_c * nv_c <= 2^26.  Weights are > 0.  Longer knot vectors return
+ *    NURBS_EINVAL before anything is launched.
  *  - Knot spans are half-open, U_k <= u < U_{k+1}; a parameter equal to the
  *    last domain knot U_{nu_c} belongs to span nu_c-1.  Parameters are
  *    clamped into [U_p, U_{nu_c}] (the clamp carries no gradient).
@@ -44,7 +46,11 @@
  *    device only with the NURBS_VALIDATE flag; without it such inputs are
  *    undefined behaviour (parameters outside the domain are clamped).
  *  - Results are deterministic: no floating-point atomics are used, and a
- *    surface's result does not depend on the other surfaces of its batch.
+ *    surface's result does not depend on the other surfaces of its batch
+ *    for a given tiling (nurbs_ctx_set_tiling): the tiling fixes the
+ *    summation order of the backward.  Plans built with different tilings
+ *    (for instance by an autotuner choosing per batch) agree within the
+ *    FP32 tolerances, not bit for bit.
  */
 #ifndef NURBSDIFF_H
 #define NURBSDIFF_H
@@ -57,6 +63,7 @@ extern "C" {
 #endif
 
 #define NURBS_MAX_DEGREE 7
+#define NURBS_MAX_KNOTS 256 /* entries per knot vector (staged whole in LDS) */
 
 /* status codes */
 #define NURBS_OK 0

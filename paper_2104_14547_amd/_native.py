@@ -30,6 +30,7 @@ NURBS_GRAD_KV = 8
 NURBS_GRAD_ALL = 15
 NURBS_VALIDATE = 1
 NURBS_MAX_DEGREE = 7
+NURBS_MAX_KNOTS = 256
 
 # every symbol include/nurbsdiff.h declares
 EXPORTS = (

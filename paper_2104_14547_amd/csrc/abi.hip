@@ -92,8 +92,9 @@ int check_shape(nurbs_ctx* c, int p, int q, int nu_c, int nv_c, int nu_s, int nv
     if (nu_c < p + 1 || nv_c < q + 1) return fail(c, NURBS_EDEGREE, "fewer control points than degree+1");
     if (nu_s < 0 || nv_s < 0) return fail(c, NURBS_EINVAL, "negative sample count");
     if ((long long)nu_c * nv_c > (1ll << 26)) return fail(c, NURBS_EINVAL, "control grid too large");
-    if (nu_c + p + 1 > kWG || nv_c + q + 1 > kWG)
-        return fail(c, NURBS_EINVAL, "knot vector longer than " + std::to_string(kWG));
+    static_assert(NURBS_MAX_KNOTS == kWG, "knot vectors are staged in kWG-entry LDS buffers");
+    if (nu_c + p + 1 > NURBS_MAX_KNOTS || nv_c + q + 1 > NURBS_MAX_KNOTS)
+        return fail(c, NURBS_EINVAL, "knot vector longer than " + std::to_string(NURBS_MAX_KNOTS));
     return NURBS_OK;
 }
 

@@ -358,7 +358,7 @@ struct BwdState {
     bool cross;       // some segment crosses a 16-lane row boundary
     float m[6];       // per-step "same segment as the source lane" multipliers
     bool head;        // last lane of its segment
-    bool wide;        // the tile touches more than 64 - QM control columns (second gather pass)
+    bool wide;        // the tile may touch more than 64 control columns (one gather pass per 64)
     unsigned hl[2];   // bytes: head lane of key (lane - h) for h = 0..7, 0xFF = none
     int q;            // degree in v (uniform, <= QM)
     float f[QM + 1];  // dL/dNv_h(v_b) partial
@@ -514,41 +514,58 @@ __device__ __forceinline__ void flush_row(const Surf& s, BwdState<QM>& st, const
     if (!want_pw) return;
     // control column j0 + c collects, for every h, the run sum of the key
     // kfirst + c - h; one h at a time through a 64-entry LDS buffer
-    float4 acc0 = make_float4(0.f, 0.f, 0.f, 0.f), acc1 = acc0;
+    float4* out = rect + (size_t)(i - i0) * st.ncols;
+    if (!st.wide) {
+        // every column of the tile in one pass; head lanes from the per-tile table
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-    for (int h = 0; h <= QM; ++h) {
-        if (h > q) continue;
-        const float c = st.act ? st.Nv[h] : 0.f;
-        float4 x = make_float4(c * G.x, c * G.y, c * G.z, c * G.w);
-        seg_scan4(x, st);
-        if (st.head) L->col[lane] = x;
-        wave_lds_sync();
-        {   // first 64 columns: head lane from the per-tile table
+        for (int h = 0; h <= QM; ++h) {
+            if (h > q) continue;
+            const float c = st.act ? st.Nv[h] : 0.f;
+            float4 x = make_float4(c * G.x, c * G.y, c * G.z, c * G.w);
+            seg_scan4(x, st);
+            if (st.head) L->col[lane] = x;
+            wave_lds_sync();
             const int hl = (int)((st.hl[h >> 2] >> (8 * (h & 3))) & 0xFFu);
             if (hl != 0xFF) {
                 const float4 v = L->col[hl];
-                acc0.x += v.x;
-                acc0.y += v.y;
-                acc0.z += v.z;
-                acc0.w += v.w;
+                acc.x += v.x;
+                acc.y += v.y;
+                acc.z += v.z;
+                acc.w += v.w;
             }
+            wave_lds_sync();
         }
-        if (st.wide) {  // columns 64.. (rare)
-            const int o = lane + kWave - h;
-            const int hl = o < st.nkeys ? (int)L->head_of[o] : -1;
+        if (lane < st.ncols) out[lane] = acc;
+        return;
+    }
+    // Wide tiles (rare: the tile's samples skip spans, so its control
+    // columns outnumber the lanes): one gather pass per 64 columns, each
+    // redoing the q+1 run sums, which keeps one accumulator live.  The
+    // column range has at most nv_c <= kWG - 2 entries, so four passes at most.
+    for (int c0 = 0; c0 < st.ncols; c0 += kWave) {
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int h = 0; h <= QM; ++h) {
+            if (h > q) continue;
+            const float c = st.act ? st.Nv[h] : 0.f;
+            float4 x = make_float4(c * G.x, c * G.y, c * G.z, c * G.w);
+            seg_scan4(x, st);
+            if (st.head) L->col[lane] = x;
+            wave_lds_sync();
+            const int o = lane + c0 - h;
+            const int hl = (o >= 0 && o < st.nkeys) ? (int)L->head_of[o] : -1;
             if (hl >= 0) {
                 const float4 v = L->col[hl];
-                acc1.x += v.x;
-                acc1.y += v.y;
-                acc1.z += v.z;
-                acc1.w += v.w;
+                acc.x += v.x;
+                acc.y += v.y;
+                acc.z += v.z;
+                acc.w += v.w;
             }
+            wave_lds_sync();
         }
-        wave_lds_sync();
+        if (lane + c0 < st.ncols) out[lane + c0] = acc;
     }
-    float4* out = rect + (size_t)(i - i0) * st.ncols;
-    if (lane < st.ncols) out[lane] = acc0;
-    if (lane + kWave < st.ncols) out[lane + kWave] = acc1;
 }
 
 // Column set-up of a backward tile (independent of the degree in u): the

@@ -177,40 +177,7 @@ def test_batch_bicubic_full_size():
     check_grads(b, grads, G_or)
 
 
-def one_surface(seed, p, q, nu_c, nv_c, nu_s, nv_s, repeat=0.0, on_knots=False, clustered=False):
-    g = np.random.Generator(np.random.PCG64(seed))
-    d = dict(p=p, q=q, nu_c=nu_c, nv_c=nv_c, nu_s=nu_s, nv_s=nv_s)
-    d["ctrl"] = W.perturbed_lattice(g, nu_c, nv_c)
-    d["w"] = g.uniform(0.5, 1.5, (nu_c, nv_c)).astype(np.float32)
-    d["ku"] = W.clamped_random_knots(g, nu_c, p, repeat)
-    d["kv"] = W.clamped_random_knots(g, nv_c, q, repeat)
-    if clustered:
-        n_int = nu_c - p - 1
-        d["ku"][p + 1:p + 1 + n_int] = (0.4 + 2e-5 * np.arange(n_int)).astype(np.float32)
-    d["us"] = W.uniform_grid(nu_s)
-    d["vs"] = W.uniform_grid(nv_s)
-    if on_knots:
-        ku_in = np.unique(d["ku"])
-        d["us"] = np.sort(np.concatenate([d["us"][:max(nu_s - len(ku_in), 0)], ku_in]))[:nu_s].astype(np.float32)
-        kv_in = np.unique(d["kv"])
-        d["vs"] = np.sort(np.concatenate([d["vs"][:max(nv_s - len(kv_in), 0)], kv_in]))[:nv_s].astype(np.float32)
-    d["upstream"] = g.uniform(-0.1, 0.1, (nu_s, nv_s, 3)).astype(np.float32)
-    return d
-
-
-EDGE = [
-    # (p, q, nu_c, nv_c, nu_s, nv_s, repeat, on_knots, clustered)
-    (1, 1, 2, 2, 1, 1, 0.0, False, False),
-    (1, 2, 3, 5, 7, 3, 0.0, False, False),
-    (3, 3, 4, 4, 64, 64, 0.0, False, False),      # Bezier patch, exactly one column block
-    (2, 3, 30, 40, 10, 13, 0.0, False, False),    # samples sparser than spans
-    (5, 5, 6, 9, 130, 200, 0.3, False, False),    # ragged row tiles and column blocks
-    (7, 7, 8, 9, 65, 129, 0.0, False, False),     # degree-7 class
-    (3, 2, 9, 9, 257, 65, 0.3, True, False),      # samples on knots, repeated knots
-    (4, 1, 12, 3, 33, 300, 0.4, True, False),
-    (3, 3, 12, 12, 40, 40, 0.0, False, True),     # clustered knots
-    (6, 2, 40, 48, 20, 250, 0.2, False, False),
-]
+from tests.cases import EDGE, one_surface  # noqa: E402
 
 
 @pytest.mark.parametrize("i", range(len(EDGE)))
@@ -372,29 +339,43 @@ def test_autograd_function_matches_direct_backward():
     assert ctrl2.grad is not None
 
 
-def test_full_size_uneven_batch_sampled():
-    """The 4096-surface batch in the benchmark's launch configuration; the
-    oracle recomputes a sample of surfaces exactly."""
+def test_full_size_uneven_batch_every_surface():
+    """The 4096-surface batch in the benchmark's launch configuration (the
+    tiling the autotuner picks, as bench.py does) and in the default one:
+    every surface against the oracle."""
+    from paper_2104_14547_amd import api
     full = W.uneven_batch(3, n_surf=4096)
-    sb, pts, grads = plan_run(full, full.upstream)
-    g = np.random.Generator(np.random.PCG64(11))
-    idx = sorted(g.choice(full.n, 40, replace=False).tolist())
-    sub = full.subset(idx)
-    S_or, G_or = oracle_both(sub, sub.upstream)
-    # gather the sampled surfaces from the full results
-    got_pts = np.zeros(sub.n_pts_floats, np.float32)
-    got_g = [np.zeros(len(getattr(sub, k)), np.float32) for k in ("ctrl", "w", "ku", "kv")]
-    for new, old in enumerate(idx):
-        p, q, nu_c, nv_c, nu_s, nv_s = (int(x) for x in full.shapes[old])
-        o_new, o_old = sub.offsets[new], full.offsets[old]
-        n = nu_s * nv_s * 3
-        got_pts[o_new[6]:o_new[6] + n] = pts[o_old[6]:o_old[6] + n]
-        sl_new, sl_old = grad_slices(sub, new), grad_slices(full, old)
-        for k, name in enumerate(("ctrl", "w", "ku", "kv")):
-            got_g[k][sl_new[name]] = grads[k][sl_old[name]]
-    check_points(sub, got_pts, S_or)
-    check_grads(sub, got_g, G_or)
-    assert np.isfinite(pts).all()
+    S_or, G_or = oracle_both(full, full.upstream)
+    args = [T(getattr(full, k)) for k in ("ctrl", "w", "ku", "kv", "us", "vs")]
+    up = T(full.upstream)
+    tuned, report = api.autotune(full.shapes, full.offsets, args, up, device=0)
+    print("autotuned tiling", report["chosen"], flush=True)
+    default = nd.SurfaceBatch(full.shapes, full.offsets, device=0)
+    for plan in (tuned, default):
+        pts = H(plan.forward(*args))
+        grads = [H(g) for g in plan.backward(*args, up)]
+        torch.cuda.synchronize()
+        assert np.isfinite(pts).all()
+        check_points(full, pts, S_or)
+        check_grads(full, grads, G_or)
+
+
+def test_full_size_fit_first_step():
+    """The 64x64-control, 512x512-sample fitting problem: its first forward
+    and backward against the oracle, at the initial (flat, unit-weight)
+    surface and at a perturbed rational one."""
+    b = W.fit_target(2)
+    g = np.random.Generator(np.random.PCG64(21))
+    perturbed = W.fit_target(2)
+    perturbed.ctrl = (perturbed.ctrl + g.uniform(-0.004, 0.004, perturbed.ctrl.shape)).astype(np.float32)
+    perturbed.w = g.uniform(0.5, 1.5, perturbed.w.shape).astype(np.float32)
+    for batch in (b, perturbed):
+        S_or = O.fwd(batch, local=True)
+        up = loss_upstream(batch, S_or)
+        G_or = O.bwd(batch, up.astype(np.float64), local=True)
+        pts, grads = uniform_run(batch, up)
+        check_points(batch, pts, S_or)
+        check_grads(batch, grads, G_or)
 
 
 # --------------------------------------------------------------------------
