@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FLUSH_BYTES = 512 << 20  # larger than the 256 MB MALL
 METRIC = "surface pts/s fwd+bwd (fp32, err≤1e-5 vs fp64 oracle); p50/p99 served latency"
 
 
@@ -67,9 +68,9 @@ def algorithmic_bytes(shapes):
             "fin": 16 * cps + 4 * kn}
 
 
-def traffic_for(kernel: str, workload: str):
+def traffic_for(kernel: str, workload: str, tiles: dict):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel sources; else None."""
+    were taken on the current kernel sources at the same tiling; else None."""
     path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -77,10 +78,28 @@ def traffic_for(kernel: str, workload: str):
         rec = json.load(fh)
     if rec.get("kernel_source_digest") != kernel_source_digest():
         return None
+    if rec.get("tiles") != tiles:
+        return None
     k = rec.get("kernels", {}).get(kernel)
     if not k:
         return None
     return k.get("hbm_bytes_per_launch")
+
+
+def timed_steps(torch, step, n: int, flush=None):
+    """Run ``step`` n times between HIP events on the current stream; with
+    ``flush`` (a large device buffer), fill it before each step, outside the
+    events.  Returns the per-step times in ms."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        if flush is not None:
+            flush.fill_(0.0)
+        a.record()
+        step()
+        b.record()
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in ev])
 
 
 def cpu_baseline(batch, sample: int, seed: int = 17):
@@ -173,6 +192,57 @@ def served_leg(batch, n_req: int, seed: int = 4):
     return out
 
 
+def uniform_leg(steps: int):
+    """The 256-surface bicubic batch (16x16 control points, 128x128 samples
+    each) through the uniform-batch calls -- the paper's
+    surface(ctrl, w, ku, kv, p, q, uv) and its backward -- with all four
+    gradients; one step (forward + backward) is captured as a HIP graph and
+    replayed, the MALL flushed before each step outside its events.  Parity
+    on every surface of the timed outputs."""
+    import torch
+    from paper_2104_14547_amd import api
+    from paper_2104_14547_amd import workloads as W
+    b = W.batch_bicubic(1)
+    b.upstream = np.random.Generator(np.random.PCG64(9)).uniform(-0.1, 0.1, b.n_pts_floats).astype(np.float32)
+    dev = torch.device("cuda", 0)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    B, p, q, nc, ns = b.n, 3, 3, 16, 128
+    ctrl, w = T(b.ctrl.reshape(B, nc, nc, 3)), T(b.w.reshape(B, nc, nc))
+    ku, kv = T(b.ku.reshape(B, -1)), T(b.kv.reshape(B, -1))
+    us = T(b.surface(0)["us"])
+    vs = T(b.surface(0)["vs"])
+    g = T(b.upstream.reshape(B, ns, ns, 3))
+    pts = torch.empty((B, ns, ns, 3), dtype=torch.float32, device=dev)
+    grads = [None]
+
+    def body():
+        api.surface_fwd(ctrl, w, ku, kv, p, q, us, vs, out=pts)
+        grads[0] = api.surface_bwd(ctrl, w, ku, kv, p, q, us, vs, g)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            body()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        body()
+    torch.cuda.synchronize()
+    flush = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
+    ms = timed_steps(torch, graph.replay, steps, flush=flush)
+    del flush
+    par = parity_all(b, pts.reshape(-1).cpu().numpy(), [x.reshape(-1).cpu().numpy() for x in grads[0]])
+    ms_step = float(np.mean(ms))
+    ab = algorithmic_bytes(b.shapes)
+    return {"workload": b.name, "api": "uniform batch (nurbs_surface_fwd / nurbs_surface_bwd), HIP graph",
+            "points": b.n_points, "steps": steps, "ms_per_step": ms_step,
+            "pts_per_s": b.n_points / (ms_step * 1e-3) if par["pass"] else None,
+            "step_algorithmic_GBs": (ab["fwd"] + ab["bwd"] + ab["fin"]) / (ms_step * 1e-3) / 1e9,
+            "parity": par}
+
+
 def fit_leg(steps: int):
     """The fitting loop (64x64 bicubic net, 512x512 samples of
     z = sin 3x cos 3y, Adam lr 1e-2 on points, weights and knots), one HIP
@@ -227,6 +297,8 @@ def main():
     ap.add_argument("--served-requests", type=int, default=3000,
                     help="requests per arrival rate in the served leg (0: skip it)")
     ap.add_argument("--fit-steps", type=int, default=500, help="steps of the fitting leg (0: skip it)")
+    ap.add_argument("--uniform-steps", type=int, default=20,
+                    help="steps of the 256-surface bicubic uniform-batch leg (0: skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (scale for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -286,20 +358,21 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # back to back, for reference: the MALL (256 MB) may still hold part of
+    # the previous step's data
+    t_bb = timed_steps(torch, step, args.steps, flush=None)
+    # the timed steps: before each, a 512 MB fill evicts the MALL, outside the
+    # events that time the step, so every step reads its inputs from HBM
+    flush = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
     plan.set_timing(args.steps)
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        step()
-    end.record()
-    torch.cuda.synchronize()
-    elapsed_ms = start.elapsed_time(end)
+    step_ms = timed_steps(torch, step, args.steps, flush=flush)
     kf, kb, kz = plan.read_timing()
     plan.set_timing(0)
-    ms_step = elapsed_ms / args.steps
-    value = batch.n_points * args.steps / (elapsed_ms / 1e3)
-    log(f"[bench] {args.steps} steps in {elapsed_ms:.3f} ms: {ms_step:.4f} ms/step, {value:.4e} pts/s; "
+    del flush
+    ms_step = float(np.mean(step_ms))
+    value = batch.n_points / (ms_step * 1e-3)
+    log(f"[bench] {args.steps} steps: {ms_step:.4f} ms/step (MALL flushed), {value:.4e} pts/s; "
+        f"back to back {np.mean(t_bb):.4f} ms/step; "
         f"kernels fwd {kf.mean():.4f} ms, bwd {kb.mean():.4f} ms, finalize {kz.mean():.4f} ms")
 
     ab = algorithmic_bytes(batch.shapes)
@@ -309,7 +382,8 @@ def main():
     achieved = ab[dom] / (avg[dom] * 1e-3) / 1e9
     kernels = {names[k]: {"avg_ms": avg[k], "algorithmic_bytes": ab[k],
                           "achieved_GBs": ab[k] / (avg[k] * 1e-3) / 1e9} for k in avg}
-    traffic = traffic_for(names[dom], args.workload)
+    chosen = tune["chosen"] if tune else {"fwd_tile_points": 16384, "bwd_tile_points": 16384}
+    traffic = traffic_for(names[dom], args.workload, chosen)
 
     result = {
         "metric": METRIC,
@@ -327,11 +401,15 @@ def main():
         "config": {"workload": batch.name, "surfaces": batch.n, "points": ab["points"],
                    "control_points": ab["control_points"], "degrees": "p,q in 1..5",
                    "launches_per_step": 3,
-                   "tiles": tune["chosen"] if tune else "default (16384 points)"},
+                   "tiles": chosen},
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "kernels": kernels,
         "step_algorithmic_GBs": (ab["fwd"] + ab["bwd"] + ab["fin"]) / (ms_step * 1e-3) / 1e9,
+        "timing": {"step_ms": "mean of per-step HIP events; a 512 MB fill evicts the MALL before each step, "
+                              "outside the events",
+                   "back_to_back_ms_per_step": float(np.mean(t_bb)),
+                   "back_to_back_pts_s": batch.n_points / (float(np.mean(t_bb)) * 1e-3)},
     }
     if tune and not tune.get("fixed"):
         result["autotune_ms"] = {d: {str(k): v for k, v in tune[d].items()} for d in ("fwd", "bwd")}
@@ -343,6 +421,10 @@ def main():
             # a throughput at failed parity is no measurement
             result["value"] = None
             log("[bench] PARITY FAILED: value withheld")
+    if args.uniform_steps > 0:
+        t1 = time.perf_counter()
+        result["batch_bicubic"] = uniform_leg(args.uniform_steps)
+        log(f"[bench] batch_bicubic {result['batch_bicubic']} ({time.perf_counter() - t1:.1f} s)")
     if args.fit_steps > 0:
         t1 = time.perf_counter()
         result["fit"] = fit_leg(args.fit_steps)

@@ -147,6 +147,26 @@ int nurbs_surface_fwd(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
                       const float *vs, int uv_shared, float *pts, void *ws,
                       size_t ws_bytes, void *stream);
 
+/* Parametric derivatives and unit normals on the same grid (Appendix A,
+ * eq. NURBSuDerivative1: S_u = (A_u - S w_u) / w, with A the homogeneous
+ * point sum and A_u its sum over dN_i/du; S_v likewise), the quantities
+ * surface offsetting moves points along (Sec. 4.3).  Inputs as
+ * nurbs_surface_fwd.  Outputs, each [B][nu_s][nv_s][3] and each optional
+ * (NULL: not computed, at least one must be given):
+ *   pts     : S (the same values as nurbs_surface_fwd up to the last ulp of
+ *             the divide);
+ *   pts_du  : dS/du;   pts_dv : dS/dv;
+ *   normals : (S_u x S_v) / |S_u x S_v|, and (0, 0, 0) where S_u x S_v = 0.
+ * The derivatives are one-sided at knots: they are those of the span the
+ * parameter falls in (half-open spans, the last one closed).  No workspace
+ * is needed except under NURBS_VALIDATE (256 bytes for the error word). */
+int nurbs_surface_derivs(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
+                         const float *ctrl, const float *w, const float *ku,
+                         const float *kv, int nu_s, int nv_s, const float *us,
+                         const float *vs, int uv_shared, float *pts, float *pts_du,
+                         float *pts_dv, float *normals, void *ws, size_t ws_bytes,
+                         void *stream);
+
 /* Vector-Jacobian product.  grad_pts = dL/dS [B][nu_s][nv_s][3].  Outputs
  * (each overwritten when its grad_mask bit is set, untouched and allowed to
  * be NULL otherwise): grad_ctrl [B][nu_c][nv_c][3], grad_w [B][nu_c][nv_c],

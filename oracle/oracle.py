@@ -199,5 +199,14 @@ def surface_bwd(ctrl, w, ku, kv, p, q, us, vs, grad_pts, local=False):
     return gc.reshape(nu_c, nv_c, 3), gw.reshape(nu_c, nv_c), gku, gkv
 
 
+def normals(Su, Sv):
+    """Unit normals (S_u x S_v) / |S_u x S_v| from the oracle's parametric
+    derivatives (Appendix A, eq. NURBSuDerivative1); offset surfaces move
+    points along them (Sec. 4.3).  (0, 0, 0) where the cross product is 0."""
+    c = np.cross(np.asarray(Su, np.float64), np.asarray(Sv, np.float64))
+    n = np.linalg.norm(c, axis=-1, keepdims=True)
+    return np.where(n > 0, c / np.where(n > 0, n, 1.0), 0.0)
+
+
 def max_threads() -> int:
     return int(lib().oracle_max_threads())

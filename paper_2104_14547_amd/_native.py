@@ -37,7 +37,7 @@ EXPORTS = (
     "nurbs_ctx_create", "nurbs_ctx_destroy", "nurbs_ctx_set_flags", "nurbs_ctx_set_knot_sigma",
     "nurbs_ctx_set_tiling",
     "nurbs_status_string", "nurbs_last_error", "nurbs_ctx_device_info",
-    "nurbs_surface_ws_bytes", "nurbs_surface_fwd", "nurbs_surface_bwd",
+    "nurbs_surface_ws_bytes", "nurbs_surface_fwd", "nurbs_surface_derivs", "nurbs_surface_bwd",
     "nurbs_plan_create", "nurbs_plan_create_in", "nurbs_plan_destroy", "nurbs_plan_info", "nurbs_plan_fwd", "nurbs_plan_bwd",
     "nurbs_plan_set_timing", "nurbs_plan_read_timing",
     "nurbs_find_spans", "nurbs_basis", "nurbs_read_device_error",
@@ -70,6 +70,8 @@ _SIGS = {
     "nurbs_surface_ws_bytes": (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, _u, _szp]),
     "nurbs_surface_fwd": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _i, _vp,
                                _vp, _sz, _vp]),
+    "nurbs_surface_derivs": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _i, _vp, _vp,
+                                  _vp, _vp, _vp, _sz, _vp]),
     "nurbs_surface_bwd": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _i, _vp,
                                _vp, _vp, _vp, _vp, _u, _vp, _sz, _vp]),
     "nurbs_plan_create": (_i, [_vp, ctypes.POINTER(nurbs_desc), _i, _u, ctypes.POINTER(_vp), _szp]),

@@ -153,6 +153,27 @@ def surface_fwd(ctrl, w, ku, kv, p: int, q: int, us, vs, out=None, ctx: Context 
     return out[0] if squeeze else out
 
 
+def surface_derivs(ctrl, w, ku, kv, p: int, q: int, us, vs, want=("pts", "du", "dv", "normals"),
+                   ctx: Context | None = None):
+    """Points, parametric derivatives dS/du, dS/dv and unit normals of a
+    uniform batch (nurbs_surface_derivs).  Returns a dict with the requested
+    keys, each [B, nu_s, nv_s, 3] (or [nu_s, nv_s, 3] for one surface)."""
+    squeeze = ctrl.dim() == 3
+    ctrl, w, ku, kv, B, nu_c, nv_c, nu_s, nv_s, shared = _uniform_shapes(ctrl, w, ku, kv, p, q, us, vs)
+    names = ("pts", "du", "dv", "normals")
+    if not want or any(k not in names for k in want):
+        raise ValueError(f"want must be a non-empty subset of {names}")
+    ctx = ctx or context(ctrl.device.index)
+    out = {k: torch.empty((B, nu_s, nv_s, 3), dtype=torch.float32, device=ctrl.device) for k in want}
+    ws = torch.zeros(256, dtype=torch.uint8, device=ctrl.device) if ctx.validate else None
+    ctx.last_ws = ws
+    _check(N.lib().nurbs_surface_derivs(ctx.handle, B, p, q, nu_c, nv_c, _ptr(ctrl), _ptr(w), _ptr(ku), _ptr(kv),
+                                        nu_s, nv_s, _ptr(us), _ptr(vs), shared,
+                                        *[_ptr(out.get(k)) for k in names], _ptr(ws), 0 if ws is None else 256,
+                                        _stream(ctrl.device)), ctx.handle)
+    return {k: (v[0] if squeeze else v) for k, v in out.items()}
+
+
 def surface_bwd(ctrl, w, ku, kv, p: int, q: int, us, vs, grad_pts, mask: int = N.NURBS_GRAD_ALL,
                 ctx: Context | None = None):
     """(dL/dctrl, dL/dw, dL/dku, dL/dkv) of a uniform batch (nurbs_surface_bwd).

@@ -272,6 +272,32 @@ int nurbs_surface_fwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, c
     return NURBS_OK;
 }
 
+int nurbs_surface_derivs(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, const float* ctrl,
+                         const float* w, const float* ku, const float* kv, int nu_s, int nv_s, const float* us,
+                         const float* vs, int uv_shared, float* pts, float* pts_du, float* pts_dv, float* normals,
+                         void* ws, size_t ws_bytes, void* stream) {
+    int rc = uniform_common(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
+    if (rc) return rc;
+    if (!pts && !pts_du && !pts_dv && !normals) return fail(ctx, NURBS_EINVAL, "no output requested");
+    if (B == 0 || nu_s == 0 || nv_s == 0) return NURBS_OK;
+    if (!ctrl || !w || !ku || !kv || !us || !vs) return fail(ctx, NURBS_EINVAL, "NULL array");
+    if ((ctx->flags & NURBS_VALIDATE) && (!ws || ws_bytes < kWsHeader))
+        return fail(ctx, NURBS_EWORKSPACE, "NURBS_VALIDATE needs a workspace");
+    const UniformGeom g = uniform_geom(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
+    if (g.tiles_f > (1ll << 30)) return fail(ctx, NURBS_EINVAL, "batch too large");
+    UniformArgs a = make_uargs(ctx, g, false, B, nu_c, nv_c, nu_s, nv_s, ctrl, w, ku, kv, us, vs, uv_shared, ws);
+    const dim3 grid((unsigned)((g.tiles_f + kWavesPerWG - 1) / kWavesPerWG));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipErrorInvalidValue;
+    switch (p) {
+#define ND_CASE(P) case P: e = launch_uniform_der_p##P(q, grid, st, a, pts, pts_du, pts_dv, normals); break;
+        ND_CASE(1) ND_CASE(2) ND_CASE(3) ND_CASE(4) ND_CASE(5) ND_CASE(6) ND_CASE(7)
+#undef ND_CASE
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "launch derivatives");
+    return NURBS_OK;
+}
+
 int nurbs_surface_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, const float* ctrl,
                       const float* w, const float* ku, const float* kv, int nu_s, int nv_s, const float* us,
                       const float* vs, int uv_shared, const float* grad_pts, float* grad_ctrl, float* grad_w,

@@ -38,6 +38,9 @@ __device__ __forceinline__ float bcast_lane(float x, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uniform_f(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
 __device__ __forceinline__ long long uniform64(long long x) {
     const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(x & 0xffffffffll));
     const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)x >> 32));
@@ -263,6 +266,15 @@ __device__ __forceinline__ float4 load_pw(const Surf& s, int i, int j) {
     return make_float4(c[0] * wt, c[1] * wt, c[2] * wt, wt);
 }
 
+// Three consecutive floats as one 12-byte store (global_store_dwordx3): a
+// wave writes a row's 64 points as 768 contiguous bytes with one instruction
+// instead of three strided ones.  Points are only 4-byte aligned.
+typedef float float3u __attribute__((ext_vector_type(3))) __attribute__((aligned(4)));
+__device__ __forceinline__ void store3(float* p, float x, float y, float z) {
+    float3u v = {x, y, z};
+    *reinterpret_cast<float3u*>(p) = v;
+}
+
 __device__ __forceinline__ float4 fma4(float a, float4 x, float4 y) {
     return make_float4(__builtin_fmaf(a, x.x, y.x), __builtin_fmaf(a, x.y, y.y),
                        __builtin_fmaf(a, x.z, y.z), __builtin_fmaf(a, x.w, y.w));
@@ -314,6 +326,38 @@ __device__ __forceinline__ int sample_basis(const float* __restrict__ U, int nc,
     const float xc = clamp_param(U, D, n, x);
     const int k = find_span(U, D, n, xc);
     basis_f32<D>(U, k, xc, N);
+    return k;
+}
+
+// The D+1 non-zero basis functions on span k and their first derivatives in
+// x (Appendix A, eq. NURBSuDerivative1 needs dN/du):
+//   dN_i^D = D N_i^{D-1} / (U_{i+D} - U_i) - D N_{i+1}^{D-1} / (U_{i+D+1} - U_{i+1}),
+// from the degree D-1 functions of the same span.  Each denominator contains
+// [U_k, U_{k+1}], so it is positive on a non-empty span.
+template <int D>
+__device__ __forceinline__ void basis_d1_f32(const float* __restrict__ U, int k, float x, float N[D + 1],
+                                             float dN[D + 1]) {
+    float Nm[D];
+    basis_f32<D - 1>(U, k, x, Nm);  // N_{k-D+1..k}^{D-1}
+#pragma unroll
+    for (int r = 0; r <= D; ++r) {
+        const int i = k - D + r;
+        float d = 0.0f;
+        if (r >= 1) d += Nm[r - 1] * recip(U[i + D] - U[i]);
+        if (r <= D - 1) d -= Nm[r] * recip(U[i + D + 1] - U[i + 1]);
+        dN[r] = (float)D * d;
+    }
+    basis_f32<D>(U, k, x, N);
+}
+
+// Span, basis and first derivatives of one sample along a direction.
+template <int D>
+__device__ __forceinline__ int sample_basis_d1(const float* __restrict__ U, int nc, float x, float N[D + 1],
+                                               float dN[D + 1]) {
+    const int n = nc - 1;
+    const float xc = clamp_param(U, D, n, x);
+    const int k = find_span(U, D, n, xc);
+    basis_d1_f32<D>(U, k, xc, N, dN);
     return k;
 }
 

@@ -39,11 +39,18 @@ namespace nd {
 // --------------------------------------------------------------------------
 // workspace layout of one backward tile (bytes from the slot start):
 //   [0, 16)                      int4 header {i0, i1, j0, j1}
-//   [16, 16 + 16*rect_cap)       float4 rect [(i1-i0+1)][(j1-j0+1)]
+//   [16, 32)                     float4 {cx, cy, cz, 0}: the tile's frame origin
+//   [32, 32 + 16*rect_cap)       float4 rect [(i1-i0+1)][(j1-j0+1)]
 //   then float e[rows][P+1], then float f[64][Q+1]
+// The rect holds dL/dPw in the tile's translated frame (control points
+// P - c): the xyz part does not depend on the frame, the w part is
+// dL/dw - (P - c) . dL/dPw_xyz of the tile's points.
 // --------------------------------------------------------------------------
+constexpr int kSlotHead = 32;
+
 struct SlotView {
     int* hdr;
+    float4* center;
     float4* rect;
     float* e;
     float* f;
@@ -52,7 +59,7 @@ struct SlotView {
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 __host__ __device__ inline size_t slot_bytes(int p, int q, int nu_c, int nv_c, int rows) {
-    size_t b = 16 + 16 * (size_t)nu_c * nv_c;
+    size_t b = kSlotHead + 16 * (size_t)nu_c * nv_c;
     b += align16(sizeof(float) * (size_t)rows * (p + 1));
     b += align16(sizeof(float) * (size_t)kWave * (q + 1));
     return b;
@@ -61,8 +68,9 @@ __host__ __device__ inline size_t slot_bytes(int p, int q, int nu_c, int nv_c, i
 __device__ __forceinline__ SlotView slot_view(char* base, int p, int nu_c, int nv_c, int rows) {
     SlotView v;
     v.hdr = reinterpret_cast<int*>(base);
-    v.rect = reinterpret_cast<float4*>(base + 16);
-    char* e = base + 16 + 16 * (size_t)nu_c * nv_c;
+    v.center = reinterpret_cast<float4*>(base + 16);
+    v.rect = reinterpret_cast<float4*>(base + kSlotHead);
+    char* e = base + kSlotHead + 16 * (size_t)nu_c * nv_c;
     v.e = reinterpret_cast<float*>(e);
     v.f = reinterpret_cast<float*>(e + align16(sizeof(float) * (size_t)rows * (p + 1)));
     return v;
@@ -294,12 +302,8 @@ __device__ __forceinline__ void fwd_rows(const Surf& s, Block& bk, const float N
                 }
                 const float rw = recip_fast(acc.w), rw2 = recip_fast(acc2.w);
                 if (act) {
-                    orow[0] = acc.x * rw;
-                    orow[1] = acc.y * rw;
-                    orow[2] = acc.z * rw;
-                    orow[ostride + 0] = acc2.x * rw2;
-                    orow[ostride + 1] = acc2.y * rw2;
-                    orow[ostride + 2] = acc2.z * rw2;
+                    store3(orow, acc.x * rw, acc.y * rw, acc.z * rw);
+                    store3(orow + ostride, acc2.x * rw2, acc2.y * rw2, acc2.z * rw2);
                 }
                 orow += 2 * ostride;
                 ++t;
@@ -309,11 +313,7 @@ __device__ __forceinline__ void fwd_rows(const Surf& s, Block& bk, const float N
 #pragma unroll
             for (int r = 0; r <= P; ++r) acc = fma4(bcast_lane(Nu_l[r], t), R[r], acc);
             const float rw = recip_fast(acc.w);
-            if (act) {
-                orow[0] = acc.x * rw;
-                orow[1] = acc.y * rw;
-                orow[2] = acc.z * rw;
-            }
+            if (act) store3(orow, acc.x * rw, acc.y * rw, acc.z * rw);
             orow += ostride;
         }
     }
@@ -344,6 +344,120 @@ __device__ __forceinline__ void fwd_tile(const Surf& sg, int q, int col0, int ro
 }
 
 // --------------------------------------------------------------------------
+// parametric derivatives and unit normals (Appendix A, eq.
+// NURBSuDerivative1: S_u = (A_u - S w_u) / w with A = sum N_i N_j Pw_ij the
+// homogeneous point; the normals S_u x S_v / |S_u x S_v| are what surface
+// offsetting moves points along, Sec. 4.3).  Same tiles as the forward, with
+// two contracted windows per lane: R_i(b) with Nv and Rv_i(b) with dNv/dv.
+// --------------------------------------------------------------------------
+struct DerOut {
+    float* pts;  // S      [nu_s][nv_s][3], or NULL
+    float* du;   // dS/du  [nu_s][nv_s][3], or NULL
+    float* dv;   // dS/dv  [nu_s][nv_s][3], or NULL
+    float* nrm;  // unit normal (0 where S_u x S_v vanishes), or NULL
+};
+
+template <int P, int QM, bool BLK>
+__device__ __forceinline__ void der_rows(const Surf& s, Block& bk, const float Nv[QM + 1], const float dNv[QM + 1],
+                                         int q, int jb, bool act, int row0, int row1, float u0, const DerOut& o,
+                                         size_t off, size_t ostride) {
+    const int lane = lane_id();
+    float4 R[P + 1], Rv[P + 1];
+    int cur = -1;  // window rows cur-P .. cur
+    for (int a0 = row0; a0 < row1; a0 += kWave) {
+        const int nr = min(kWave, row1 - a0);
+        float Nu_l[P + 1], dNu_l[P + 1];
+        const float ua = a0 == row0 ? u0 : s.us[a0 + min(lane, nr - 1)];
+        const int ka_l = sample_basis_d1<P>(s.ku, s.nu_c, ua, Nu_l, dNu_l);
+        for (int t = 0; t < nr; ++t, off += ostride) {
+            const int ka = bcast_lane(ka_l, t);
+            if (ka != cur) {
+                ensure_rows<BLK>(s, bk, ka - P, ka);
+                if (cur >= 0 && ka > cur && ka - cur <= P) {
+                    do {
+#pragma unroll
+                        for (int r = 0; r < P; ++r) {
+                            R[r] = R[r + 1];
+                            Rv[r] = Rv[r + 1];
+                        }
+                        ++cur;
+                        R[P] = blk_contract<QM, BLK>(s, bk, cur, jb, Nv, q);
+                        Rv[P] = blk_contract<QM, BLK>(s, bk, cur, jb, dNv, q);
+                    } while (cur < ka);
+                } else {
+                    cur = ka;
+#pragma unroll
+                    for (int r = 0; r <= P; ++r) {
+                        R[r] = blk_contract<QM, BLK>(s, bk, ka - P + r, jb, Nv, q);
+                        Rv[r] = blk_contract<QM, BLK>(s, bk, ka - P + r, jb, dNv, q);
+                    }
+                }
+            }
+            float4 A = make_float4(0.f, 0.f, 0.f, 0.f), Au = A, Av = A;
+#pragma unroll
+            for (int r = 0; r <= P; ++r) {
+                A = fma4(bcast_lane(Nu_l[r], t), R[r], A);
+                Au = fma4(bcast_lane(dNu_l[r], t), R[r], Au);
+                Av = fma4(bcast_lane(Nu_l[r], t), Rv[r], Av);
+            }
+            const float rw = recip(A.w);
+            const float sx = A.x * rw, sy = A.y * rw, sz = A.z * rw;
+            const float ux = (Au.x - sx * Au.w) * rw, uy = (Au.y - sy * Au.w) * rw, uz = (Au.z - sz * Au.w) * rw;
+            const float vx = (Av.x - sx * Av.w) * rw, vy = (Av.y - sy * Av.w) * rw, vz = (Av.z - sz * Av.w) * rw;
+            if (!act) continue;
+            if (o.pts) store3(o.pts + off, sx, sy, sz);
+            if (o.du) store3(o.du + off, ux, uy, uz);
+            if (o.dv) store3(o.dv + off, vx, vy, vz);
+            if (o.nrm) {
+                const float nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
+                const float l2 = nx * nx + ny * ny + nz * nz;
+                const float il = l2 > 0.f ? __builtin_amdgcn_rsqf(l2) : 0.f;
+                store3(o.nrm + off, nx * il, ny * il, nz * il);
+            }
+        }
+    }
+}
+
+template <int P, int QM>
+__device__ __forceinline__ void der_tile(const Surf& sg, int q, int col0, int row0, int row1, const DerOut& o,
+                                         FwdLds* lds) {
+    const int lane = lane_id();
+    Surf s = sg;
+    const TileIn in = stage_tile(sg, P, q, col0, row0, row1, lds->knots[0], lds->knots[1]);
+    s.ku = lds->knots[0];
+    s.kv = lds->knots[1];
+    float Nv[QM + 1], dNv[QM + 1];
+#pragma unroll
+    for (int h = 0; h <= QM; ++h) Nv[h] = dNv[h] = 0.f;
+    const int b = col0 + lane;
+    const bool act = b < s.nv_s;
+    int kb = 0;
+    switch (q) {
+#define ND_DV(D)                                                                        \
+    case D:                                                                             \
+        if constexpr (D <= QM) {                                                        \
+            float n_[D + 1], d_[D + 1];                                                 \
+            kb = sample_basis_d1<D>(s.kv, s.nv_c, in.v, n_, d_);                        \
+            _Pragma("unroll") for (int h = 0; h <= D; ++h) { Nv[h] = n_[h]; dNv[h] = d_[h]; } \
+        }                                                                               \
+        break;
+        ND_DV(1) ND_DV(2) ND_DV(3) ND_DV(4) ND_DV(5) ND_DV(6) ND_DV(7)
+#undef ND_DV
+        default: break;
+    }
+    const int nact = min(kWave, s.nv_s - col0);
+    const int kfirst = bcast_lane(kb, 0), klast = bcast_lane(kb, nact - 1);
+    const int j0 = kfirst - q;
+    Block bk = make_block(lds->blk, j0, klast - j0 + 1, P);
+    const size_t off = 3 * ((size_t)row0 * s.nv_s + b);
+    const size_t ostride = 3 * (size_t)s.nv_s;
+    if (bk.on)
+        der_rows<P, QM, true>(s, bk, Nv, dNv, q, kb - q, act, row0, row1, in.u0, o, off, ostride);
+    else
+        der_rows<P, QM, false>(s, bk, Nv, dNv, q, kb - q, act, row0, row1, in.u0, o, off, ostride);
+}
+
+// --------------------------------------------------------------------------
 // backward tile
 // --------------------------------------------------------------------------
 template <int QM>
@@ -362,6 +476,7 @@ struct BwdState {
     unsigned hl[2];   // bytes: head lane of key (lane - h) for h = 0..7, 0xFF = none
     int q;            // degree in v (uniform, <= QM)
     float f[QM + 1];  // dL/dNv_h(v_b) partial
+    float cx, cy, cz; // the tile's frame origin (a control point of the tile, uniform)
 };
 
 // per-wave LDS of the backward tile, sized for degrees p <= PM
@@ -491,6 +606,17 @@ __device__ __forceinline__ void seg_scan2(float& x, float& y, const Runs& r) {
     }
 }
 
+// A contracted row R = sum_h Nv_h Pw in the tile's frame translated by c:
+// Pw - c w, i.e. (R_xyz - c R_w, R_w).  The backward works in this frame so
+// that its sums of -(g . S)/W carry |S - c| (the tile's extent) instead of
+// |S|; dL/dw, the small difference P . dL/dPw_xyz + dL/dPw_w of two such
+// sums, then keeps its FP32 accuracy on nets far from the origin.
+template <class St>
+__device__ __forceinline__ float4 center4(float4 R, const St& st) {
+    return make_float4(__builtin_fmaf(-st.cx, R.w, R.x), __builtin_fmaf(-st.cy, R.w, R.y),
+                       __builtin_fmaf(-st.cz, R.w, R.z), R.w);
+}
+
 // Flush control row i (accumulator G) of the tile: dV partial and the rect
 // row i - i0 of dL/dPw.  Row i is staged in the block (or read from global).
 template <int QM, bool BLK>
@@ -500,15 +626,23 @@ __device__ __forceinline__ void flush_row(const Surf& s, BwdState<QM>& st, const
     const int lane = lane_opaque();
     const int q = st.q;
     if (want_kv) {
+        // (Pw - c w) . G = Pw . G - w (c . G_xyz)
+        const float cg = __builtin_fmaf(st.cx, G.x, __builtin_fmaf(st.cy, G.y, st.cz * G.z));
         if constexpr (BLK) {
             const float4* row = block_row(bk, i, st.jb);
 #pragma unroll
             for (int h = 0; h <= QM; ++h)
-                if (h <= q) st.f[h] += dot4(row[h], G);
+                if (h <= q) {
+                    const float4 pw = row[h];
+                    st.f[h] += __builtin_fmaf(-pw.w, cg, dot4(pw, G));
+                }
         } else {
 #pragma unroll
             for (int h = 0; h <= QM; ++h)
-                if (h <= q) st.f[h] += dot4(load_pw(s, i, st.jb + h), G);
+                if (h <= q) {
+                    const float4 pw = load_pw(s, i, st.jb + h);
+                    st.f[h] += __builtin_fmaf(-pw.w, cg, dot4(pw, G));
+                }
         }
     }
     if (!want_pw) return;
@@ -660,9 +794,19 @@ __device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, B
                 cur = ka;
                 i0 = ka - P;
                 ensure_rows<BLK>(s, bk, ka - P, ka);
+                {   // frame origin: the control point in the middle of the first window
+                    const int ic = ka - P + P / 2, jc = st.j0 + (st.ncols - 1) / 2;
+                    float4 pc;
+                    if constexpr (BLK) pc = *block_row(bk, ic, jc);
+                    else pc = load_pw(s, ic, jc);
+                    const float rw = recip(pc.w);
+                    st.cx = uniform_f(pc.x * rw);
+                    st.cy = uniform_f(pc.y * rw);
+                    st.cz = uniform_f(pc.z * rw);
+                }
 #pragma unroll
                 for (int r = 0; r <= P; ++r) {
-                    R[r] = blk_contract<QM, BLK>(s, bk, ka - P + r, st.jb, st.Nv, q);
+                    R[r] = center4(blk_contract<QM, BLK>(s, bk, ka - P + r, st.jb, st.Nv, q), st);
                     G[r] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
             } else {
@@ -678,7 +822,7 @@ __device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, B
                     ++cur;
                     G[P] = make_float4(0.f, 0.f, 0.f, 0.f);
                     ensure_rows<BLK>(s, bk, cur - P, cur);
-                    R[P] = blk_contract<QM, BLK>(s, bk, cur, st.jb, st.Nv, q);
+                    R[P] = center4(blk_contract<QM, BLK>(s, bk, cur, st.jb, st.Nv, q), st);
                 }
             }
             float Nu[P + 1];
@@ -730,6 +874,7 @@ __device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, B
         out.hdr[1] = i1;
         out.hdr[2] = st.j0;
         out.hdr[3] = st.j0 + st.ncols - 1;
+        *out.center = make_float4(st.cx, st.cy, st.cz, 0.f);
     }
 }
 
@@ -926,10 +1071,12 @@ __device__ __forceinline__ void fin_pw_chunk(const Surf& s, int ntiles, TileAt t
         ii[c] = ij / s.nv_c;
         jj[c] = ij - ii[c] * s.nv_c;
     }
-    auto load_tile = [&](int t, float4 v[kFinCp]) {
+    // v: the tile's rect entries; c: its frame origin
+    auto load_tile = [&](int t, float4 v[kFinCp], float4& c) {
         const char* slot = tile_at(t).slot;
+        c = *reinterpret_cast<const float4*>(slot + 16);
         const int4 h = hdr_lds ? L->hdr[t] : *reinterpret_cast<const int4*>(slot);
-        const float4* rect = reinterpret_cast<const float4*>(slot + 16);
+        const float4* rect = reinterpret_cast<const float4*>(slot + kSlotHead);
         const int pitch = h.w - h.z + 1;
 #pragma unroll
         for (int c = 0; c < kFinCp; ++c) {
@@ -938,28 +1085,30 @@ __device__ __forceinline__ void fin_pw_chunk(const Surf& s, int ntiles, TileAt t
             v[c] = in ? rect[(size_t)(ii[c] - h.x) * pitch + (jj[c] - h.z)] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     };
-    auto add = [&](const float4 v[kFinCp]) {
+    // acc.w collects dL/dw - P . dL/dPw_xyz: the tile's rect w (its frame's
+    // dL/dw - (P - c) . dL/dPw_xyz) minus c . dL/dPw_xyz
+    auto add = [&](const float4 v[kFinCp], const float4 ct) {
 #pragma unroll
         for (int c = 0; c < kFinCp; ++c) {
             acc[c].x += v[c].x;
             acc[c].y += v[c].y;
             acc[c].z += v[c].z;
-            acc[c].w += v[c].w;
+            acc[c].w += v[c].w - (ct.x * v[c].x + ct.y * v[c].y + ct.z * v[c].z);
         }
     };
     // two tiles' loads in flight at a time; sums still in tile order
     int t = 0;
     for (; t + 1 < ntiles; t += 2) {
-        float4 va[kFinCp], vb[kFinCp];
-        load_tile(t, va);
-        load_tile(t + 1, vb);
-        add(va);
-        add(vb);
+        float4 va[kFinCp], vb[kFinCp], ca, cb;
+        load_tile(t, va, ca);
+        load_tile(t + 1, vb, cb);
+        add(va, ca);
+        add(vb, cb);
     }
     if (t < ntiles) {
-        float4 va[kFinCp];
-        load_tile(t, va);
-        add(va);
+        float4 va[kFinCp], ca;
+        load_tile(t, va, ca);
+        add(va, ca);
     }
 #pragma unroll
     for (int c = 0; c < kFinCp; ++c) {
@@ -989,7 +1138,7 @@ __device__ __forceinline__ void fin_knots_u(const Surf& s, int ntiles, TileAt ti
         const int rb = a / rows;
         for (int cb = 0; cb < ncb; ++cb) {
             const TileRef tr = tile_at(rb * ncb + cb);
-            const float* ev = reinterpret_cast<const float*>(tr.slot + 16 + rect_bytes) +
+            const float* ev = reinterpret_cast<const float*>(tr.slot + kSlotHead + rect_bytes) +
                               (size_t)(a - tr.row0) * (P + 1);
 #pragma unroll
             for (int r = 0; r <= P; ++r) e[r] += ev[r];
@@ -1013,7 +1162,7 @@ __device__ __forceinline__ void fin_knots_v(const Surf& s, int ntiles, TileAt ti
         for (int rb = 0; rb < nrb; ++rb) {
             const TileRef tr = tile_at(rb * ncb + cb);
             const float* fv = reinterpret_cast<const float*>(
-                tr.slot + 16 + rect_bytes + align16(sizeof(float) * (size_t)tr.alloc_rows * (p + 1)));
+                tr.slot + kSlotHead + rect_bytes + align16(sizeof(float) * (size_t)tr.alloc_rows * (p + 1)));
 #pragma unroll
             for (int h = 0; h <= Q; ++h) f[h] += fv[(b - tr.col0) * (Q + 1) + h];
         }

@@ -63,6 +63,8 @@ struct PlanArgs {
 #define ND_DECLARE_UNIFORM(P)                                                                          \
     hipError_t launch_uniform_fwd_p##P(int q, dim3 grid, hipStream_t st, const UniformArgs& a,         \
                                        float* pts);                                                    \
+    hipError_t launch_uniform_der_p##P(int q, dim3 grid, hipStream_t st, const UniformArgs& a,         \
+                                       float* pts, float* du, float* dv, float* nrm);                  \
     hipError_t launch_uniform_bwd_p##P(int q, dim3 grid, hipStream_t st, const UniformArgs& a,         \
                                        const float* gpts, char* slots, size_t slot_sz, unsigned mask); \
     hipError_t launch_uniform_fin_p##P(int q, dim3 grid, hipStream_t st, const UniformArgs& a,         \

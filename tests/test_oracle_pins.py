@@ -337,6 +337,28 @@ def test_parametric_derivative_matches_finite_difference():
     np.testing.assert_allclose(Sv, fdv, atol=1e-6)
 
 
+def test_normals_of_cylinder_and_plane():
+    """The quarter cylinder's unit normal is radial, (x, y, 0), pointing out
+    (S_u runs along the arc counter-clockwise, S_v along +z); a net in the
+    plane z = 0 with u along +x and v along +y has normal +z whatever its
+    weights."""
+    ctrl, w, ku, kv = quarter_cylinder()
+    us, vs = np.linspace(0, 1, 17), np.linspace(0, 1, 4)
+    S, Su, Sv = O.surface_fwd(ctrl, w, ku, kv, 2, 1, us, vs, derivs=True)
+    n = O.normals(Su, Sv)
+    np.testing.assert_allclose(n[..., :2], S[..., :2], atol=1e-13)
+    np.testing.assert_allclose(n[..., 2], 0.0, atol=1e-15)
+    g = rng(23)
+    p, q, nu_c, nv_c = 3, 2, 7, 6
+    i, j = np.meshgrid(np.arange(nu_c), np.arange(nv_c), indexing="ij")
+    flat = np.stack([i / (nu_c - 1), j / (nv_c - 1), np.zeros(i.shape)], -1)
+    flat[..., :2] += g.uniform(-0.05, 0.05, flat[..., :2].shape)
+    w = g.uniform(0.5, 1.5, (nu_c, nv_c))
+    _, Su, Sv = O.surface_fwd(flat, w, rand_knots(g, nu_c, p), rand_knots(g, nv_c, q), p, q,
+                              g.uniform(0, 1, 9), g.uniform(0, 1, 8), derivs=True)
+    np.testing.assert_allclose(O.normals(Su, Sv), np.broadcast_to([0, 0, 1.0], Su.shape), atol=1e-12)
+
+
 # --------------------------------------------------------------------------
 # gradients
 # --------------------------------------------------------------------------
