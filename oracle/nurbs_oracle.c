@@ -586,3 +586,150 @@ int oracle_bwd(int nsurf, const int32_t *shapes, const int64_t *offs,
     }
     return err;
 }
+
+/* ---------------------------------------------------------------------- */
+/* curves                                                                   */
+/* ---------------------------------------------------------------------- */
+/* A rational B-spline curve C(u) = sum_i N_i^p(u) w_i P_i / sum_i N_i^p(u) w_i
+ * with P_i in R^dim (dim 2 or 3): eq. (NURBS) with one parametric direction
+ * dropped, the way Sec. 3 obtains curves from the surface formulas.  Its
+ * derivatives are those of Sec. 3.2.1 with the v direction dropped:
+ *   dC/dP_i = N_i w_i / W                      (eq. NURBSuDerivative4)
+ *   dC/dw_i = N_i (P_i - C) / W                (eq. NURBSvDerivative5)
+ *   dC/dN_i = w_i (P_i - C) / W                (eq. NURBSvDerivative6)
+ * times dN_i/dU_k from the recursion's knot duals for the knots, and
+ *   dC/du   = (A_u W - A W_u) / W^2            (eq. NURBSuDerivative1)
+ * with A = sum_i N_i w_i P_i, W = sum_i N_i w_i.  Dense mode only: every
+ * basis function of the knot vector at every sample.
+ *
+ * Packed batch convention: for curve s,
+ *   shapes[4*s + 0..3] = p, nc, ns, dim
+ *   offs[5*s + 0..4]   = element offsets of ctrl [nc][dim], w [nc],
+ *                        knots [nc+p+1], us [ns], pts [ns][dim];
+ *   gradients reuse the offsets of the arrays they are gradients of. */
+
+static int check_curve(int p, int nc, int ns, int dim, const double *U, const double *w)
+{
+    if (p < 1 || p > OR_PMAX || nc < p + 1) return OR_EDEGREE;
+    if (ns < 0 || (dim != 2 && dim != 3)) return OR_EARG;
+    const int nU = nc + p + 1;
+    for (int i = 0; i + 1 < nU; ++i) if (!(U[i] <= U[i + 1])) return OR_EKNOTS;
+    if (!(U[p] < U[p + 1]) || !(U[nc - 1] < U[nc])) return OR_EKNOTS;
+    for (int i = 0; i < nc; ++i) if (!(w[i] > 0.0)) return OR_EWEIGHTS;
+    return OR_OK;
+}
+
+static int curve_fwd(int p, int nc, int ns, int dim, const double *P, const double *w,
+                     const double *U, const double *us, double *C, double *Cu)
+{
+    int rc = check_curve(p, nc, ns, dim, U, w);
+    if (rc) return rc;
+    const int nU = nc + p + 1;
+    double *N = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *dN = (double *)malloc(sizeof(double) * (size_t)nc);
+    if (!N || !dN) { free(N); free(dN); return OR_ENOMEM; }
+    for (int a = 0; a < ns && rc == OR_OK; ++a) {
+        rc = oracle_basis_dense(U, nU, p, us[a], N, NULL, dN);
+        double A[3] = {0, 0, 0}, Wsum = 0.0, Au[3] = {0, 0, 0}, Wu = 0.0;
+        for (int i = 0; i < nc; ++i) {
+            const double c = N[i] * w[i], cu = dN[i] * w[i];
+            for (int x = 0; x < dim; ++x) {
+                A[x] += c * P[(size_t)i * dim + x];
+                Au[x] += cu * P[(size_t)i * dim + x];
+            }
+            Wsum += c;
+            Wu += cu;
+        }
+        for (int x = 0; x < dim; ++x) {
+            C[(size_t)a * dim + x] = A[x] / Wsum;
+            if (Cu) Cu[(size_t)a * dim + x] = (Au[x] * Wsum - A[x] * Wu) / (Wsum * Wsum);
+        }
+    }
+    free(N);
+    free(dN);
+    return rc;
+}
+
+static int curve_bwd(int p, int nc, int ns, int dim, const double *P, const double *w,
+                     const double *U, const double *us, const double *G,
+                     double *dP, double *dW, double *dU)
+{
+    int rc = check_curve(p, nc, ns, dim, U, w);
+    if (rc) return rc;
+    const int nU = nc + p + 1;
+    double *N = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *dNdU = (double *)malloc(sizeof(double) * (size_t)nc * nU);
+    if (!N || !dNdU) { free(N); free(dNdU); return OR_ENOMEM; }
+    memset(dP, 0, sizeof(double) * (size_t)nc * dim);
+    memset(dW, 0, sizeof(double) * (size_t)nc);
+    memset(dU, 0, sizeof(double) * (size_t)nU);
+    for (int a = 0; a < ns && rc == OR_OK; ++a) {
+        rc = oracle_basis_dense(U, nU, p, us[a], N, dNdU, NULL);
+        const double *g = G + (size_t)a * dim;
+        double A[3] = {0, 0, 0}, Wsum = 0.0;
+        for (int i = 0; i < nc; ++i) {
+            const double c = N[i] * w[i];
+            for (int x = 0; x < dim; ++x) A[x] += c * P[(size_t)i * dim + x];
+            Wsum += c;
+        }
+        double C[3];
+        for (int x = 0; x < dim; ++x) C[x] = A[x] / Wsum;
+        for (int i = 0; i < nc; ++i) {
+            double pg = 0.0; /* (P_i - C) . g */
+            for (int x = 0; x < dim; ++x) {
+                dP[(size_t)i * dim + x] += N[i] * w[i] / Wsum * g[x];
+                pg += (P[(size_t)i * dim + x] - C[x]) * g[x];
+            }
+            dW[i] += N[i] * pg / Wsum;
+            const double coef = w[i] * pg / Wsum; /* dL/dN_i at this sample */
+            for (int k = 0; k < nU; ++k) dU[k] += coef * dNdU[(size_t)i * nU + k];
+        }
+    }
+    free(N);
+    free(dNdU);
+    return rc;
+}
+
+/* C (and optionally dC/du) for every curve of a packed batch. */
+int oracle_curve_fwd(int ncurve, const int32_t *shapes, const int64_t *offs,
+                     const double *ctrl, const double *w, const double *knots,
+                     const double *us, double *pts, double *pts_du, int nthreads)
+{
+    int err = OR_OK;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int s = 0; s < ncurve; ++s) {
+        const int32_t *sh = shapes + 4 * (size_t)s;
+        const int64_t *o = offs + 5 * (size_t)s;
+        int rc = curve_fwd(sh[0], sh[1], sh[2], sh[3], ctrl + o[0], w + o[1], knots + o[2],
+                           us + o[3], pts + o[4], pts_du ? pts_du + o[4] : NULL);
+        if (rc) {
+#pragma omp critical
+            if (!err) err = rc;
+        }
+    }
+    return err;
+}
+
+/* dL/dP, dL/dw, dL/dU of every curve given dL/dC (grad_pts). */
+int oracle_curve_bwd(int ncurve, const int32_t *shapes, const int64_t *offs,
+                     const double *ctrl, const double *w, const double *knots,
+                     const double *us, const double *grad_pts, double *grad_ctrl,
+                     double *grad_w, double *grad_knots, int nthreads)
+{
+    int err = OR_OK;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int s = 0; s < ncurve; ++s) {
+        const int32_t *sh = shapes + 4 * (size_t)s;
+        const int64_t *o = offs + 5 * (size_t)s;
+        int rc = curve_bwd(sh[0], sh[1], sh[2], sh[3], ctrl + o[0], w + o[1], knots + o[2],
+                           us + o[3], grad_pts + o[4], grad_ctrl + o[0], grad_w + o[1],
+                           grad_knots + o[2]);
+        if (rc) {
+#pragma omp critical
+            if (!err) err = rc;
+        }
+    }
+    return err;
+}

@@ -59,6 +59,10 @@ def lib():
         L.oracle_fwd.argtypes = [ctypes.c_int, _ip, _lp] + [_dp] * 9 + [ctypes.c_int, ctypes.c_int]
         L.oracle_bwd.restype = ctypes.c_int
         L.oracle_bwd.argtypes = [ctypes.c_int, _ip, _lp] + [_dp] * 11 + [ctypes.c_int, ctypes.c_int]
+        L.oracle_curve_fwd.restype = ctypes.c_int
+        L.oracle_curve_fwd.argtypes = [ctypes.c_int, _ip, _lp] + [_dp] * 6 + [ctypes.c_int]
+        L.oracle_curve_bwd.restype = ctypes.c_int
+        L.oracle_curve_bwd.argtypes = [ctypes.c_int, _ip, _lp] + [_dp] * 8 + [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -197,6 +201,87 @@ def surface_bwd(ctrl, w, ku, kv, p, q, us, vs, grad_pts, local=False):
     nu_c, nv_c, nu_s, nv_s = one.dims
     gc, gw, gku, gkv = bwd(one, np.asarray(grad_pts, np.float64).ravel(), local=local)
     return gc.reshape(nu_c, nv_c, 3), gw.reshape(nu_c, nv_c), gku, gkv
+
+
+# --------------------------------------------------------------------------
+# curves: eq. (NURBS) with one parametric direction dropped (Sec. 3)
+# --------------------------------------------------------------------------
+
+def _curve_args(cb):
+    shapes = np.ascontiguousarray(cb.shapes, np.int32)
+    offs = np.ascontiguousarray(cb.offsets, np.int64)
+    keep = [shapes, offs]
+    ptrs = []
+    for name in ("ctrl", "w", "knots", "us"):
+        a, p = _d(getattr(cb, name))
+        keep.append(a)
+        ptrs.append(p)
+    return keep, shapes.ctypes.data_as(_ip), offs.ctypes.data_as(_lp), ptrs
+
+
+def _curve_pts_len(cb):
+    s = np.asarray(cb.shapes, np.int64)
+    o = np.asarray(cb.offsets, np.int64)
+    return int((o[:, 4] + s[:, 2] * s[:, 3]).max()) if len(s) else 0
+
+
+def curve_fwd(cb, derivs: bool = False, nthreads: int = 0):
+    """Curve points (packed [ns][dim] per curve, float64) of a packed curve
+    batch ``cb`` (shapes (p, nc, ns, dim), offsets (ctrl, w, knots, us, pts));
+    with ``derivs`` also dC/du."""
+    keep, sh, of, ptrs = _curve_args(cb)
+    n = _curve_pts_len(cb)
+    pts = np.zeros(n)
+    du = np.zeros(n) if derivs else None
+    rc = lib().oracle_curve_fwd(len(cb.shapes), sh, of, *ptrs, pts.ctypes.data_as(_dp),
+                                du.ctypes.data_as(_dp) if derivs else _null(), int(nthreads))
+    del keep
+    if rc:
+        raise OracleError(rc)
+    return (pts, du) if derivs else pts
+
+
+def curve_bwd(cb, grad_pts, nthreads: int = 0):
+    """(dL/dctrl, dL/dw, dL/dknots) of a packed curve batch, float64."""
+    keep, sh, of, ptrs = _curve_args(cb)
+    g, gp = _d(grad_pts)
+    gc, gw, gk = np.zeros(len(cb.ctrl)), np.zeros(len(cb.w)), np.zeros(len(cb.knots))
+    rc = lib().oracle_curve_bwd(len(cb.shapes), sh, of, *ptrs, gp, gc.ctypes.data_as(_dp),
+                                gw.ctypes.data_as(_dp), gk.ctypes.data_as(_dp), int(nthreads))
+    del keep, g
+    if rc:
+        raise OracleError(rc)
+    return gc, gw, gk
+
+
+class _OneCurve:
+    def __init__(self, ctrl, w, U, p, us):
+        ctrl = np.asarray(ctrl, np.float64)
+        nc, dim = ctrl.shape
+        us = np.atleast_1d(np.asarray(us, np.float64))
+        self.shapes = np.array([[p, nc, len(us), dim]], np.int32)
+        self.offsets = np.zeros((1, 5), np.int64)
+        self.ctrl, self.w = ctrl.ravel(), np.asarray(w, np.float64).ravel()
+        self.knots, self.us = np.asarray(U, np.float64), us
+        self.dims = (nc, len(us), dim)
+
+
+def curve_eval(ctrl, w, U, p, us, derivs=False):
+    """Dense-array convenience: C[ns][dim] (and dC/du) of one curve."""
+    one = _OneCurve(ctrl, w, U, p, us)
+    nc, ns, dim = one.dims
+    r = curve_fwd(one, derivs=derivs)
+    if derivs:
+        return r[0].reshape(ns, dim), r[1].reshape(ns, dim)
+    return r.reshape(ns, dim)
+
+
+def curve_grad(ctrl, w, U, p, us, G):
+    """Dense-array convenience: (dP[nc][dim], dW[nc], dU[nc+p+1]) of one curve."""
+    one = _OneCurve(ctrl, w, U, p, us)
+    nc, ns, dim = one.dims
+    gc, gw, gk = curve_bwd(one, np.asarray(G, np.float64).ravel())
+    return gc.reshape(nc, dim), gw, gk
 
 
 def normals(Su, Sv):

@@ -12,6 +12,7 @@ import subprocess
 import pytest
 
 from oracle import oracle as O
+from tests import test_oracle_curve_pins as TC
 from tests import test_oracle_pins as T
 
 MUTANTS = {
@@ -40,6 +41,15 @@ MUTANTS = {
     "dSdN_drop": ("for (int x = 0; x < 3; ++x) c += g[x] * (num[x] / Wsum - NR[x] / W2 * den);\n                rowsum[ci] = c;",
                   "for (int x = 0; x < 3; ++x) c += g[x] * (num[x] / Wsum);\n                rowsum[ci] = c;"),
     # last-span rule lost: u == U_{n+1} falls off the end
+    # curve: sign error in (P_i - C) of the weight and knot derivatives
+    "curve_dW_sign": ("pg += (P[(size_t)i * dim + x] - C[x]) * g[x];",
+                      "pg += (P[(size_t)i * dim + x] + C[x]) * g[x];"),
+    # curve: rational basis without its weight
+    "curve_dP_no_weight": ("dP[(size_t)i * dim + x] += N[i] * w[i] / Wsum * g[x];",
+                           "dP[(size_t)i * dim + x] += N[i] / Wsum * g[x];"),
+    # curve: dC/du drops the denominator's derivative
+    "curve_du_drop": ("(Au[x] * Wsum - A[x] * Wu) / (Wsum * Wsum)",
+                      "(Au[x] * Wsum) / (Wsum * Wsum)"),
     "no_last_span": ("    if (u >= U[n + 1]) {\n        val[n] = 1.0;\n    } else {",
                      "    if (0) {\n        val[n] = 1.0;\n    } else {"),
 }
@@ -60,6 +70,11 @@ PINS = [
     (T.test_grad_knots_fd, (False,)),
     (T.test_grad_knots_shift_and_scale_invariance, ()),
     (T.test_dense_equals_local_surface, ()),
+    (TC.test_quarter_circle, ()),
+    (TC.test_rational_bezier_closed_form, (3,)),
+    (TC.test_curve_is_surface_edge, (0,)),
+    (TC.test_finite_differences, ()),
+    (TC.test_invariants, ()),
 ]
 
 
