@@ -28,6 +28,7 @@ _lib = None
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
 _lp = ctypes.POINTER(ctypes.c_int64)
+_fp = ctypes.POINTER(ctypes.c_float)
 
 
 def build(force: bool = True) -> str:
@@ -63,6 +64,11 @@ def lib():
         L.oracle_curve_fwd.argtypes = [ctypes.c_int, _ip, _lp] + [_dp] * 6 + [ctypes.c_int]
         L.oracle_curve_bwd.restype = ctypes.c_int
         L.oracle_curve_bwd.argtypes = [ctypes.c_int, _ip, _lp] + [_dp] * 8 + [ctypes.c_int]
+        L.oracle_nearest.restype = ctypes.c_int
+        L.oracle_nearest.argtypes = [ctypes.c_int, _fp, ctypes.c_int, _fp, ctypes.c_int, _ip, _fp, ctypes.c_int]
+        L.oracle_chamfer_hausdorff.restype = ctypes.c_int
+        L.oracle_chamfer_hausdorff.argtypes = [ctypes.c_int, _fp, ctypes.c_int, _fp, ctypes.c_int, _dp, _dp, _dp,
+                                               ctypes.c_int]
         _lib = L
     return _lib
 
@@ -295,3 +301,42 @@ def normals(Su, Sv):
 
 def max_threads() -> int:
     return int(lib().oracle_max_threads())
+
+
+# --------------------------------------------------------------------------
+# point-set losses: Sec. 4, eqs. (ChamferDistance), (HausdorffDistance)
+# --------------------------------------------------------------------------
+
+def _f32(x, dim):
+    a = np.ascontiguousarray(np.asarray(x, np.float32).reshape(-1, dim))
+    return a, a.ctypes.data_as(_fp)
+
+
+def nearest(P, Q, nthreads: int = 0):
+    """For each row of P [n][dim] the index of its nearest row of Q [m][dim]
+    and that squared distance, decided in float32 (first index wins ties)."""
+    dim = np.asarray(P).shape[-1]
+    P, pp = _f32(P, dim)
+    Q, qp = _f32(Q, dim)
+    idx = np.zeros(len(P), np.int32)
+    d2 = np.zeros(len(P), np.float32)
+    rc = lib().oracle_nearest(dim, pp, len(P), qp, len(Q), idx.ctypes.data_as(_ip), d2.ctypes.data_as(_fp),
+                              int(nthreads))
+    if rc:
+        raise OracleError(rc)
+    return idx, d2
+
+
+def chamfer_hausdorff(P, Q, nthreads: int = 0):
+    """(CD, HD, dCD/dP [n][dim], dHD/dP [n][dim]) in float64."""
+    dim = np.asarray(P).shape[-1]
+    P, pp = _f32(P, dim)
+    Q, qp = _f32(Q, dim)
+    out = np.zeros(2)
+    gcd = np.zeros((len(P), dim))
+    ghd = np.zeros((len(P), dim))
+    rc = lib().oracle_chamfer_hausdorff(dim, pp, len(P), qp, len(Q), out.ctypes.data_as(_dp),
+                                        gcd.ctypes.data_as(_dp), ghd.ctypes.data_as(_dp), int(nthreads))
+    if rc:
+        raise OracleError(rc)
+    return float(out[0]), float(out[1]), gcd, ghd

@@ -13,6 +13,7 @@ import pytest
 
 from oracle import oracle as O
 from tests import test_oracle_curve_pins as TC
+from tests import test_oracle_loss_pins as TL
 from tests import test_oracle_pins as T
 
 MUTANTS = {
@@ -50,6 +51,16 @@ MUTANTS = {
     # curve: dC/du drops the denominator's derivative
     "curve_du_drop": ("(Au[x] * Wsum - A[x] * Wu) / (Wsum * Wsum)",
                       "(Au[x] * Wsum) / (Wsum * Wsum)"),
+    # loss: squared distance used where the norm belongs
+    "loss_squared": ("    const double d = sqrt(s);\n", "    const double d = s;\n"),
+    # loss: the second (target-to-point) Chamfer term dropped
+    "loss_one_sided": ("        cd += pair_dist(dim, P + (size_t)i * dim, Q + (size_t)j * dim, dir);",
+                       "        cd += 0.0 * pair_dist(dim, P + (size_t)i * dim, Q + (size_t)j * dim, dir);"),
+    # loss: last index wins ties of the nearest-point decision
+    "loss_tie_last": ("            if (d < bd) { bd = d; best = j; }", "            if (d <= bd) { bd = d; best = j; }"),
+    # loss: gradient of the second term sent to the target's index
+    "loss_grad_index": ("            for (int x = 0; x < dim; ++x) gcd[(size_t)i * dim + x] += dir[x];\n        if (db[j]",
+                        "            for (int x = 0; x < dim; ++x) gcd[(size_t)(j % n) * dim + x] += dir[x];\n        if (db[j]"),
     "no_last_span": ("    if (u >= U[n + 1]) {\n        val[n] = 1.0;\n    } else {",
                      "    if (0) {\n        val[n] = 1.0;\n    } else {"),
 }
@@ -75,6 +86,11 @@ PINS = [
     (TC.test_curve_is_surface_edge, (0,)),
     (TC.test_finite_differences, ()),
     (TC.test_invariants, ()),
+    (TL.test_nearest_exact_on_integer_lattice_first_index_wins, ()),
+    (TL.test_identity_and_symmetry, ()),
+    (TL.test_shifted_copy_closed_form, (3,)),
+    (TL.test_hand_worked_example, ()),
+    (TL.test_finite_differences, (3,)),
 ]
 
 
