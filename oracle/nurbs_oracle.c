@@ -19,6 +19,7 @@
  *   - dN_i^p/dU_k by the chain rule up the recursion -- Sec. 3.2.1
  *   - dS/du (parametric derivative)    -- Appendix A, eq. (NURBSuDerivative1)
  *   - curves: eq. (NURBS) with one direction dropped, and its gradients -- Sec. 3
+ *   - surfaces at scattered (u, v) pairs: eq. (NURBS) at each pair
  *   - Chamfer and Hausdorff distances and their gradients
  *                                      -- Sec. 4, eqs. (ChamferDistance),
  *                                         (HausdorffDistance)
@@ -836,4 +837,53 @@ int oracle_chamfer_hausdorff(int dim, const float *P, int n, const float *Q, int
     out[1] = hd;
     free(a); free(b); free(da); free(db);
     return OR_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* scattered parameters                                                     */
+/* ---------------------------------------------------------------------- */
+/*
+ * Surface points at scattered parameter pairs (u_k, v_k), k = 0..npts-1,
+ * in any order (eq. NURBS at each pair; Sec. 3.1 evaluates a grid, which is
+ * the special case of all pairs of two parameter lists).  Each pair is the
+ * 1x1 grid {u_k} x {v_k} of the grid functions above; the gradients are the
+ * sums over the pairs of the per-pair gradients.
+ *   uv [npts][2], S / Su / Sv / G [npts][3]; dP, dW, dU, dV as for a grid.
+ */
+int oracle_scattered_fwd(int p, int q, int nu_c, int nv_c, int npts, const double *P, const double *w,
+                         const double *ku, const double *kv, const double *uv, double *S, double *Su, double *Sv,
+                         int local)
+{
+    for (int k = 0; k < npts; ++k) {
+        int rc = surface_fwd(p, q, nu_c, nv_c, 1, 1, P, w, ku, kv, uv + 2 * (size_t)k, uv + 2 * (size_t)k + 1,
+                             S + 3 * (size_t)k, Su ? Su + 3 * (size_t)k : NULL, Sv ? Sv + 3 * (size_t)k : NULL,
+                             local);
+        if (rc) return rc;
+    }
+    return OR_OK;
+}
+
+int oracle_scattered_bwd(int p, int q, int nu_c, int nv_c, int npts, const double *P, const double *w,
+                         const double *ku, const double *kv, const double *uv, const double *G, double *dP,
+                         double *dW, double *dU, double *dV, int local)
+{
+    const size_t ncp = (size_t)nu_c * nv_c, nU = (size_t)nu_c + p + 1, nV = (size_t)nv_c + q + 1;
+    double *t = (double *)malloc(sizeof(double) * (4 * ncp + nU + nV));
+    if (!t) return OR_ENOMEM;
+    double *tP = t, *tW = t + 3 * ncp, *tU = tW + ncp, *tV = tU + nU;
+    memset(dP, 0, sizeof(double) * 3 * ncp);
+    memset(dW, 0, sizeof(double) * ncp);
+    memset(dU, 0, sizeof(double) * nU);
+    memset(dV, 0, sizeof(double) * nV);
+    int rc = OR_OK;
+    for (int k = 0; k < npts && rc == OR_OK; ++k) {
+        rc = surface_bwd(p, q, nu_c, nv_c, 1, 1, P, w, ku, kv, uv + 2 * (size_t)k, uv + 2 * (size_t)k + 1,
+                         G + 3 * (size_t)k, tP, tW, tU, tV, local);
+        for (size_t i = 0; rc == OR_OK && i < 3 * ncp; ++i) dP[i] += tP[i];
+        for (size_t i = 0; rc == OR_OK && i < ncp; ++i) dW[i] += tW[i];
+        for (size_t i = 0; rc == OR_OK && i < nU; ++i) dU[i] += tU[i];
+        for (size_t i = 0; rc == OR_OK && i < nV; ++i) dV[i] += tV[i];
+    }
+    free(t);
+    return rc;
 }

@@ -64,6 +64,10 @@ def lib():
         L.oracle_curve_fwd.argtypes = [ctypes.c_int, _ip, _lp] + [_dp] * 6 + [ctypes.c_int]
         L.oracle_curve_bwd.restype = ctypes.c_int
         L.oracle_curve_bwd.argtypes = [ctypes.c_int, _ip, _lp] + [_dp] * 8 + [ctypes.c_int]
+        L.oracle_scattered_fwd.restype = ctypes.c_int
+        L.oracle_scattered_fwd.argtypes = [ctypes.c_int] * 5 + [_dp] * 8 + [ctypes.c_int]
+        L.oracle_scattered_bwd.restype = ctypes.c_int
+        L.oracle_scattered_bwd.argtypes = [ctypes.c_int] * 5 + [_dp] * 10 + [ctypes.c_int]
         L.oracle_nearest.restype = ctypes.c_int
         L.oracle_nearest.argtypes = [ctypes.c_int, _fp, ctypes.c_int, _fp, ctypes.c_int, _ip, _fp, ctypes.c_int]
         L.oracle_chamfer_hausdorff.restype = ctypes.c_int
@@ -340,3 +344,44 @@ def chamfer_hausdorff(P, Q, nthreads: int = 0):
     if rc:
         raise OracleError(rc)
     return float(out[0]), float(out[1]), gcd, ghd
+
+
+# --------------------------------------------------------------------------
+# surfaces at scattered (u, v) pairs: eq. (NURBS) at each pair
+# --------------------------------------------------------------------------
+
+def scattered_fwd(ctrl, w, ku, kv, p, q, uv, derivs=False, local=True):
+    """S [npts][3] (and S_u, S_v) of one surface at the pairs uv [npts][2]."""
+    ctrl = np.asarray(ctrl, np.float64)
+    nu_c, nv_c = ctrl.shape[:2]
+    uv = np.ascontiguousarray(np.asarray(uv, np.float64).reshape(-1, 2))
+    n = len(uv)
+    S = np.zeros((n, 3))
+    Su = np.zeros((n, 3)) if derivs else None
+    Sv = np.zeros((n, 3)) if derivs else None
+    keep = [_d(ctrl.ravel()), _d(np.asarray(w, np.float64).ravel()), _d(ku), _d(kv), _d(uv.ravel())]
+    rc = lib().oracle_scattered_fwd(int(p), int(q), nu_c, nv_c, n, *[k[1] for k in keep],
+                                    S.ctypes.data_as(_dp), Su.ctypes.data_as(_dp) if derivs else _null(),
+                                    Sv.ctypes.data_as(_dp) if derivs else _null(), int(bool(local)))
+    del keep
+    if rc:
+        raise OracleError(rc)
+    return (S, Su, Sv) if derivs else S
+
+
+def scattered_bwd(ctrl, w, ku, kv, p, q, uv, G, local=True):
+    """(dP [nu_c][nv_c][3], dW [nu_c][nv_c], dU, dV) of one surface at the pairs uv."""
+    ctrl = np.asarray(ctrl, np.float64)
+    nu_c, nv_c = ctrl.shape[:2]
+    uv = np.ascontiguousarray(np.asarray(uv, np.float64).reshape(-1, 2))
+    n = len(uv)
+    dP, dW = np.zeros((nu_c, nv_c, 3)), np.zeros((nu_c, nv_c))
+    dU, dV = np.zeros(nu_c + p + 1), np.zeros(nv_c + q + 1)
+    keep = [_d(ctrl.ravel()), _d(np.asarray(w, np.float64).ravel()), _d(ku), _d(kv), _d(uv.ravel()),
+            _d(np.asarray(G, np.float64).ravel())]
+    rc = lib().oracle_scattered_bwd(int(p), int(q), nu_c, nv_c, n, *[k[1] for k in keep],
+                                    *[a.ctypes.data_as(_dp) for a in (dP, dW, dU, dV)], int(bool(local)))
+    del keep
+    if rc:
+        raise OracleError(rc)
+    return dP, dW, dU, dV

@@ -14,6 +14,7 @@ import pytest
 from oracle import oracle as O
 from tests import test_oracle_curve_pins as TC
 from tests import test_oracle_loss_pins as TL
+from tests import test_oracle_scattered_pins as TS
 from tests import test_oracle_pins as T
 
 MUTANTS = {
@@ -61,6 +62,12 @@ MUTANTS = {
     # loss: gradient of the second term sent to the target's index
     "loss_grad_index": ("            for (int x = 0; x < dim; ++x) gcd[(size_t)i * dim + x] += dir[x];\n        if (db[j]",
                         "            for (int x = 0; x < dim; ++x) gcd[(size_t)(j % n) * dim + x] += dir[x];\n        if (db[j]"),
+    # scattered: per-pair gradients overwrite instead of accumulating
+    "scattered_overwrite": ("for (size_t i = 0; rc == OR_OK && i < 3 * ncp; ++i) dP[i] += tP[i];",
+                            "for (size_t i = 0; rc == OR_OK && i < 3 * ncp; ++i) dP[i] = tP[i];"),
+    # scattered: v read from the wrong slot of the pair
+    "scattered_v_slot": ("uv + 2 * (size_t)k, uv + 2 * (size_t)k + 1,\n                             S + 3",
+                         "uv + 2 * (size_t)k, uv + 2 * (size_t)k,\n                             S + 3"),
     "no_last_span": ("    if (u >= U[n + 1]) {\n        val[n] = 1.0;\n    } else {",
                      "    if (0) {\n        val[n] = 1.0;\n    } else {"),
 }
@@ -91,6 +98,8 @@ PINS = [
     (TL.test_shifted_copy_closed_form, (3,)),
     (TL.test_hand_worked_example, ()),
     (TL.test_finite_differences, (3,)),
+    (TS.test_shuffled_grid_equals_grid, (3, 3)),
+    (TS.test_scattered_finite_differences, ()),
 ]
 
 
