@@ -181,6 +181,43 @@ int nurbs_surface_bwd(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
                       size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Curves: B rational B-spline curves of one shape in the plane (dim 2) or in
+ * space (dim 3),
+ *     C(u) = sum_i N_i^p(u) w_i P_i / sum_i N_i^p(u) w_i,
+ * eq. NURBS with one parametric direction (Sec. 3 builds curves from the
+ * surface formulas by dropping a direction; the curve fits of Sec. 4.1).
+ *   ctrl [B][nc][dim], w [B][nc], knots [B][nc+p+1]; us [ns] if u_shared
+ *   else [B][ns]; pts, pts_du, grad_pts [B][ns][dim].
+ * Degree, knot, weight and parameter rules are those of the surface calls
+ * with one direction (1 <= p <= NURBS_MAX_DEGREE, nc >= p+1,
+ * nc+p+1 <= NURBS_MAX_KNOTS, clamped parameters, half-open spans).  The
+ * parameters need not be sorted; sorted ones take the faster reduction.
+ * Workspace: nurbs_curve_ws_bytes; 0 bytes for a forward without
+ * NURBS_VALIDATE; the backward needs at least the 256-byte header, plus one
+ * partial per 2048 samples for curves with more samples than that.
+ * ---------------------------------------------------------------------- */
+int nurbs_curve_ws_bytes(nurbs_ctx *ctx, int B, int p, int nc, int dim, int ns,
+                         unsigned grad_mask, size_t *out);
+
+/* Points C(u) and, when pts_du is not NULL, the tangents dC/du
+ * (eq. NURBSuDerivative1 with one direction: (A_u - C W_u) / W). */
+int nurbs_curve_fwd(nurbs_ctx *ctx, int B, int p, int nc, int dim, const float *ctrl,
+                    const float *w, const float *knots, int ns, const float *us,
+                    int u_shared, float *pts, float *pts_du, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* Vector-Jacobian product (Sec. 3.2 with one direction): grad_pts = dL/dC.
+ * grad_mask bits NURBS_GRAD_CTRL, NURBS_GRAD_W and NURBS_GRAD_KU (the knot
+ * vector); NURBS_GRAD_KV is rejected.  Outputs as for the surfaces:
+ * grad_ctrl [B][nc][dim], grad_w [B][nc], grad_knots [B][nc+p+1], each
+ * overwritten when its bit is set.  Deterministic (no atomics). */
+int nurbs_curve_bwd(nurbs_ctx *ctx, int B, int p, int nc, int dim, const float *ctrl,
+                    const float *w, const float *knots, int ns, const float *us,
+                    int u_shared, const float *grad_pts, float *grad_ctrl,
+                    float *grad_w, float *grad_knots, unsigned grad_mask, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Ragged batch ("plan"): thousands of surfaces of uneven degree, control
  * grid and sample grid in one persistent launch per direction (the paper's
  * batched forward of Alg. Forward over all surfaces, and Alg. Backward).

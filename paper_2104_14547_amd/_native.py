@@ -41,6 +41,7 @@ EXPORTS = (
     "nurbs_plan_create", "nurbs_plan_create_in", "nurbs_plan_destroy", "nurbs_plan_info", "nurbs_plan_fwd", "nurbs_plan_bwd",
     "nurbs_plan_set_timing", "nurbs_plan_read_timing",
     "nurbs_find_spans", "nurbs_basis", "nurbs_read_device_error",
+    "nurbs_curve_ws_bytes", "nurbs_curve_fwd", "nurbs_curve_bwd",
 )
 
 
@@ -87,6 +88,10 @@ _SIGS = {
     "nurbs_find_spans": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp]),
     "nurbs_basis": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp]),
     "nurbs_read_device_error": (_i, [_vp, _vp, _ip]),
+    "nurbs_curve_ws_bytes": (_i, [_vp, _i, _i, _i, _i, _i, _u, _szp]),
+    "nurbs_curve_fwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _sz, _vp]),
+    "nurbs_curve_bwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _u, _vp, _sz,
+                             _vp]),
 }
 
 _lib = None

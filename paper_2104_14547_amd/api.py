@@ -256,6 +256,106 @@ class NurbsSurface(torch.nn.Module):
 
 
 # --------------------------------------------------------------------------
+# curves
+# --------------------------------------------------------------------------
+
+def _curve_shapes(ctrl, w, knots, p, us):
+    for name, t in (("ctrl", ctrl), ("w", w), ("knots", knots), ("us", us)):
+        _need_cuda_f32(name, t)
+    if ctrl.dim() == 2:
+        ctrl, w, knots = ctrl[None], w[None], knots[None]
+    if ctrl.dim() != 3 or ctrl.shape[-1] not in (2, 3):
+        raise ValueError("ctrl must be [B, nc, dim] or [nc, dim] with dim 2 or 3")
+    B, nc, dim = (int(x) for x in ctrl.shape)
+    if tuple(w.shape) != (B, nc) or tuple(knots.shape) != (B, nc + p + 1):
+        raise ValueError("w must be [B, nc] and knots [B, nc+p+1]")
+    if us.dim() == 1:
+        shared, ns = 1, int(us.shape[0])
+    elif us.dim() == 2 and us.shape[0] == B:
+        shared, ns = 0, int(us.shape[1])
+    else:
+        raise ValueError("us must be [ns] (shared) or [B, ns]")
+    return ctrl, w, knots, B, nc, dim, ns, shared
+
+
+def curve_fwd(ctrl, w, knots, p: int, us, derivs: bool = False, ctx: Context | None = None):
+    """Points C[B, ns, dim] (and dC/du when ``derivs``) of B curves of one
+    shape (nurbs_curve_fwd)."""
+    squeeze = ctrl.dim() == 2
+    ctrl, w, knots, B, nc, dim, ns, shared = _curve_shapes(ctrl, w, knots, p, us)
+    ctx = ctx or context(ctrl.device.index)
+    dev = ctrl.device
+    pts = torch.empty((B, ns, dim), dtype=torch.float32, device=dev)
+    du = torch.empty_like(pts) if derivs else None
+    ws = torch.zeros(256, dtype=torch.uint8, device=dev) if ctx.validate else None
+    ctx.last_ws = ws
+    _check(N.lib().nurbs_curve_fwd(ctx.handle, B, int(p), nc, dim, _ptr(ctrl), _ptr(w), _ptr(knots), ns, _ptr(us),
+                                   shared, _ptr(pts), _ptr(du), _ptr(ws), 0 if ws is None else 256, _stream(dev)),
+           ctx.handle)
+    if squeeze:
+        pts, du = pts[0], (None if du is None else du[0])
+    return (pts, du) if derivs else pts
+
+
+def curve_bwd(ctrl, w, knots, p: int, us, grad_pts, mask: int = N.NURBS_GRAD_CTRL | N.NURBS_GRAD_W | N.NURBS_GRAD_KU,
+              ctx: Context | None = None):
+    """(dL/dctrl, dL/dw, dL/dknots) of B curves (nurbs_curve_bwd); entries
+    whose mask bit is clear are None."""
+    squeeze = ctrl.dim() == 2
+    ctrl, w, knots, B, nc, dim, ns, shared = _curve_shapes(ctrl, w, knots, p, us)
+    grad_pts = grad_pts.contiguous()
+    if squeeze:
+        grad_pts = grad_pts[None]
+    _need_cuda_f32("grad_pts", grad_pts)
+    if tuple(grad_pts.shape) != (B, ns, dim):
+        raise ValueError("grad_pts must be [B, ns, dim]")
+    ctx = ctx or context(ctrl.device.index)
+    dev = ctrl.device
+    gc = torch.empty_like(ctrl) if mask & N.NURBS_GRAD_CTRL else None
+    gw = torch.empty_like(w) if mask & N.NURBS_GRAD_W else None
+    gk = torch.empty_like(knots) if mask & N.NURBS_GRAD_KU else None
+    ws_n = ctypes.c_size_t()
+    _check(N.lib().nurbs_curve_ws_bytes(ctx.handle, B, int(p), nc, dim, ns, int(mask), ctypes.byref(ws_n)),
+           ctx.handle)
+    ws = torch.zeros(ws_n.value, dtype=torch.uint8, device=dev) if ws_n.value else None
+    ctx.last_ws = ws
+    _check(N.lib().nurbs_curve_bwd(ctx.handle, B, int(p), nc, dim, _ptr(ctrl), _ptr(w), _ptr(knots), ns, _ptr(us),
+                                   shared, _ptr(grad_pts), _ptr(gc), _ptr(gw), _ptr(gk), int(mask), _ptr(ws),
+                                   ws_n.value, _stream(dev)), ctx.handle)
+    res = (gc, gw, gk)
+    if squeeze:
+        res = tuple(None if r is None else r[0] for r in res)
+    return res
+
+
+class NurbsCurveFn(torch.autograd.Function):
+    """Differentiable curve evaluation with the library's adjoint."""
+
+    @staticmethod
+    def forward(fctx, ctrl, w, knots, p, us):
+        pts = curve_fwd(ctrl, w, knots, p, us)
+        fctx.save_for_backward(ctrl, w, knots, us)
+        fctx.p = p
+        return pts
+
+    @staticmethod
+    def backward(fctx, grad_pts):
+        ctrl, w, knots, us = fctx.saved_tensors
+        need = fctx.needs_input_grad
+        mask = (N.NURBS_GRAD_CTRL if need[0] else 0) | (N.NURBS_GRAD_W if need[1] else 0) | \
+               (N.NURBS_GRAD_KU if need[2] else 0)
+        if mask == 0:
+            return (None,) * 5
+        gc, gw, gk = curve_bwd(ctrl, w, knots, fctx.p, us, grad_pts.contiguous(), mask)
+        return gc, gw, gk, None, None
+
+
+def curve(ctrl, w, knots, p: int, us):
+    """C = curve(ctrl, w, knots, p, us), differentiable in ctrl, w and knots."""
+    return NurbsCurveFn.apply(ctrl.contiguous(), w.contiguous(), knots.contiguous(), int(p), us.contiguous())
+
+
+# --------------------------------------------------------------------------
 # ragged batches
 # --------------------------------------------------------------------------
 

@@ -351,6 +351,100 @@ int nurbs_surface_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, c
 }
 
 // --------------------------------------------------------------------------
+// curves
+// --------------------------------------------------------------------------
+namespace {
+
+int curve_common(nurbs_ctx* ctx, int B, int p, int nc, int dim, int ns) {
+    if (!ctx) return fail(nullptr, NURBS_EINVAL, "ctx is NULL");
+    if (B < 0 || ns < 0) return fail(ctx, NURBS_EINVAL, "negative batch or sample count");
+    if (dim != 2 && dim != 3) return fail(ctx, NURBS_EINVAL, "dim must be 2 or 3");
+    if (p < 1 || p > NURBS_MAX_DEGREE)
+        return fail(ctx, NURBS_EDEGREE, "degree outside [1, " + std::to_string(NURBS_MAX_DEGREE) + "]");
+    if (nc < p + 1) return fail(ctx, NURBS_EDEGREE, "fewer control points than degree+1");
+    if (nc + p + 1 > NURBS_MAX_KNOTS)
+        return fail(ctx, NURBS_EINVAL, "knot vector longer than " + std::to_string(NURBS_MAX_KNOTS));
+    return NURBS_OK;
+}
+
+CurveArgs curve_args(const nurbs_ctx* ctx, int B, int p, int nc, int ns, const float* ctrl, const float* w,
+                     const float* knots, const float* us, int u_shared, void* ws) {
+    CurveArgs a;
+    a.ctrl = ctrl; a.w = w; a.knots = knots; a.us = us;
+    a.B = B; a.nc = nc; a.ns = ns; a.u_shared = u_shared ? 1 : 0;
+    a.nchunks = std::max(1, (ns + kCurveChunk - 1) / kCurveChunk);
+    a.part_floats = (4 * nc + nc + p + 1 + 3) & ~3;
+    a.err = (ctx->flags & NURBS_VALIDATE) ? reinterpret_cast<int*>(ws) : nullptr;
+    return a;
+}
+
+size_t curve_ws_need(const CurveArgs& a, bool bwd) {
+    size_t n = (a.err || bwd) ? kWsHeader : 0;
+    if (bwd && a.nchunks > 1) n += (size_t)a.B * a.nchunks * a.part_floats * sizeof(float);
+    return n;
+}
+
+}  // namespace
+
+int nurbs_curve_ws_bytes(nurbs_ctx* ctx, int B, int p, int nc, int dim, int ns, unsigned grad_mask, size_t* out) {
+    int rc = curve_common(ctx, B, p, nc, dim, ns);
+    if (rc) return rc;
+    if (!out) return fail(ctx, NURBS_EINVAL, "out is NULL");
+    if (grad_mask & ~(NURBS_GRAD_CTRL | NURBS_GRAD_W | NURBS_GRAD_KU))
+        return fail(ctx, NURBS_EINVAL, "curve gradient bits are CTRL, W and KU (the knots)");
+    const CurveArgs a = curve_args(ctx, B, p, nc, ns, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
+    if (grad_mask == 0) *out = (ctx->flags & NURBS_VALIDATE) ? kWsHeader : 0;
+    else *out = curve_ws_need(a, true);
+    return NURBS_OK;
+}
+
+int nurbs_curve_fwd(nurbs_ctx* ctx, int B, int p, int nc, int dim, const float* ctrl, const float* w,
+                    const float* knots, int ns, const float* us, int u_shared, float* pts, float* pts_du, void* ws,
+                    size_t ws_bytes, void* stream) {
+    int rc = curve_common(ctx, B, p, nc, dim, ns);
+    if (rc) return rc;
+    if (B == 0 || ns == 0) return NURBS_OK;
+    if (!ctrl || !w || !knots || !us || !pts) return fail(ctx, NURBS_EINVAL, "NULL array");
+    if ((ctx->flags & NURBS_VALIDATE) && (!ws || ws_bytes < kWsHeader))
+        return fail(ctx, NURBS_EWORKSPACE, "NURBS_VALIDATE needs a workspace");
+    const CurveArgs a = curve_args(ctx, B, p, nc, ns, ctrl, w, knots, us, u_shared, ws);
+    if ((long long)B * a.nchunks > (1ll << 31) - 1) return fail(ctx, NURBS_EINVAL, "batch too large");
+    hipError_t e = launch_curve_fwd(p, dim, reinterpret_cast<hipStream_t>(stream), a, pts, pts_du);
+    return e ? hip_fail(ctx, e, "launch curve forward") : NURBS_OK;
+}
+
+int nurbs_curve_bwd(nurbs_ctx* ctx, int B, int p, int nc, int dim, const float* ctrl, const float* w,
+                    const float* knots, int ns, const float* us, int u_shared, const float* grad_pts,
+                    float* grad_ctrl, float* grad_w, float* grad_knots, unsigned grad_mask, void* ws,
+                    size_t ws_bytes, void* stream) {
+    int rc = curve_common(ctx, B, p, nc, dim, ns);
+    if (rc) return rc;
+    if (grad_mask & ~(NURBS_GRAD_CTRL | NURBS_GRAD_W | NURBS_GRAD_KU))
+        return fail(ctx, NURBS_EINVAL, "curve gradient bits are CTRL, W and KU (the knots)");
+    if (grad_mask == 0 || B == 0) return NURBS_OK;
+    if (((grad_mask & NURBS_GRAD_CTRL) && !grad_ctrl) || ((grad_mask & NURBS_GRAD_W) && !grad_w) ||
+        ((grad_mask & NURBS_GRAD_KU) && !grad_knots))
+        return fail(ctx, NURBS_EINVAL, "NULL gradient output for a requested gradient");
+    if (!ctrl || !w || !knots) return fail(ctx, NURBS_EINVAL, "NULL array");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (ns == 0) {
+        hipError_t e = hipSuccess;
+        if (grad_mask & NURBS_GRAD_CTRL) e = launch_zero(st, grad_ctrl, (size_t)B * nc * dim);
+        if (!e && (grad_mask & NURBS_GRAD_W)) e = launch_zero(st, grad_w, (size_t)B * nc);
+        if (!e && (grad_mask & NURBS_GRAD_KU)) e = launch_zero(st, grad_knots, (size_t)B * (nc + p + 1));
+        return e ? hip_fail(ctx, e, "zero fill") : NURBS_OK;
+    }
+    if (!us || !grad_pts) return fail(ctx, NURBS_EINVAL, "NULL us or grad_pts");
+    const CurveArgs a = curve_args(ctx, B, p, nc, ns, ctrl, w, knots, us, u_shared, ws);
+    const size_t need = curve_ws_need(a, true);
+    if (!ws || ws_bytes < need) return fail(ctx, NURBS_EWORKSPACE, "workspace too small: need " + std::to_string(need));
+    if ((long long)B * a.nchunks > (1ll << 31) - 1) return fail(ctx, NURBS_EINVAL, "batch too large");
+    float* part = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + kWsHeader);
+    hipError_t e = launch_curve_bwd(p, dim, st, a, grad_pts, grad_ctrl, grad_w, grad_knots, part, grad_mask);
+    return e ? hip_fail(ctx, e, "launch curve backward") : NURBS_OK;
+}
+
+// --------------------------------------------------------------------------
 // plans
 // --------------------------------------------------------------------------
 namespace {

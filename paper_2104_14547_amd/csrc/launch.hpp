@@ -92,6 +92,19 @@ ND_DECLARE_PLAN(5)
 ND_DECLARE_PLAN(7)
 #undef ND_DECLARE_PLAN
 
+// curves: B curves of one shape (k_curve.hip)
+constexpr int kCurveChunk = 2048;  // samples per workgroup
+struct CurveArgs {
+    const float *ctrl, *w, *knots, *us;  // [B][nc][dim], [B][nc], [B][nc+p+1], [B or 1][ns]
+    int B, nc, ns, u_shared;
+    int nchunks;      // workgroups per curve, ceil(ns / kCurveChunk)
+    int part_floats;  // floats per chunk partial in the workspace (multi-chunk curves)
+    int* err;         // device error word (NURBS_VALIDATE) or NULL
+};
+hipError_t launch_curve_fwd(int p, int dim, hipStream_t st, const CurveArgs& a, float* pts, float* du);
+hipError_t launch_curve_bwd(int p, int dim, hipStream_t st, const CurveArgs& a, const float* gpts, float* gctrl,
+                            float* gw, float* gk, float* part, unsigned mask);
+
 // test exports
 // zero n floats on stream st (a kernel, so graph capture records no memset)
 hipError_t launch_zero(hipStream_t st, float* p, size_t n);

@@ -30,6 +30,7 @@ and for its timing tables' control-net / sample-grid / degree sweeps):
   towards z = sin(3x) cos(3y).
 * ``uneven_batch``   -- 4096 surfaces, degrees 1..5, control sides 4..48 and
   sample sides 16..256 log-uniform, 10% repeated interior knots.
+* ``curve_batch``    -- B curves in the plane or in space on jittered circles.
 """
 from __future__ import annotations
 
@@ -285,6 +286,66 @@ def uneven_batch(seed: int = 3, n_surf: int = 4096, with_upstream: bool = True,
     if with_upstream:
         b.upstream = rng.uniform(-0.1, 0.1, b.n_pts_floats).astype(np.float32)
     return b
+
+
+# --------------------------------------------------------------------------
+# curves
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class CurveBatch:
+    """B rational B-spline curves of one shape (float32 inputs):
+    ``ctrl [B][nc][dim]``, ``w [B][nc]``, ``knots [B][nc+p+1]``, ``us [ns]``
+    (shared) or ``[B][ns]``, ``upstream [B][ns][dim]`` (dL/dC)."""
+
+    name: str
+    p: int
+    nc: int
+    ns: int
+    dim: int
+    ctrl: np.ndarray
+    w: np.ndarray
+    knots: np.ndarray
+    us: np.ndarray
+    upstream: np.ndarray
+
+    @property
+    def B(self) -> int:
+        return int(self.ctrl.shape[0])
+
+    @property
+    def n_points(self) -> int:
+        return self.B * self.ns
+
+
+def curve_batch(seed: int = 5, B: int = 64, p: int = 3, nc: int = 16, ns: int = 256, dim: int = 3,
+                repeat: float = 0.1, shared_u: bool = True, shuffle: bool = False) -> CurveBatch:
+    """Curves in the plane or in space, standing in for the curve fits of the
+    paper's curve-fitting section: control polygons along a jittered circle
+    (x = cos t + U(-0.2, 0.2), y = sin t + U(-0.2, 0.2), z ~ U(-0.3, 0.3)),
+    weights U(0.5, 1.5), clamped knots with sorted U(0,1) interior knots and
+    ``repeat`` repeated ones (multiplicity <= p).  Parameters: the uniform
+    grid a/(ns-1) shared by all curves, or per curve ns sorted U(0,1) draws
+    (``shared_u=False``), optionally in random order (``shuffle``).
+    dL/dC ~ U(-0.1, 0.1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = np.linspace(0.0, 2.0 * math.pi, nc, endpoint=False)[None, :] + rng.uniform(0, 2 * math.pi, (B, 1))
+    ctrl = np.zeros((B, nc, dim))
+    ctrl[..., 0] = np.cos(t) + rng.uniform(-0.2, 0.2, (B, nc))
+    ctrl[..., 1] = np.sin(t) + rng.uniform(-0.2, 0.2, (B, nc))
+    if dim == 3:
+        ctrl[..., 2] = rng.uniform(-0.3, 0.3, (B, nc))
+    w = rng.uniform(0.5, 1.5, (B, nc))
+    knots = np.stack([clamped_random_knots(rng, nc, p, repeat) for _ in range(B)])
+    if shared_u and not shuffle:
+        us = uniform_grid(ns)
+    else:
+        us = np.sort(rng.uniform(0.0, 1.0, (B, ns)), axis=1).astype(np.float32)
+        if shuffle:
+            us = np.stack([us[c][rng.permutation(ns)] for c in range(B)])
+    up = rng.uniform(-0.1, 0.1, (B, ns, dim)).astype(np.float32)
+    return CurveBatch(name=f"curves_{B}x{nc}_p{p}_{ns}_d{dim}", p=p, nc=nc, ns=ns, dim=dim,
+                      ctrl=ctrl.astype(np.float32), w=w.astype(np.float32), knots=knots, us=us, upstream=up)
 
 
 WORKLOADS = {
