@@ -180,6 +180,29 @@ int nurbs_surface_bwd(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
                       float *grad_kv, unsigned grad_mask, void *ws,
                       size_t ws_bytes, void *stream);
 
+/* The same backward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no workspace argument; the tile slots live in a 64 MiB array
+ * that the library keeps in device memory (one per device it runs on, held
+ * until the process ends).  Arguments, outputs and results as
+ * nurbs_surface_bwd, bit for bit.
+ * Limits and errors: NURBS_EWORKSPACE when the shapes need more than the
+ * 64 MiB that nurbs_surface_ws_bytes would report (use nurbs_surface_bwd
+ * with a workspace then); NURBS_EUNSUPPORTED under NURBS_VALIDATE (no data
+ * checks here); NURBS_EINVAL when the context's device is not current at
+ * the first call on that device.  The call itself allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine).
+ * Concurrency: every call on a device shares that device's array, so calls
+ * that overlap on one device (different streams, or different threads
+ * without ordering) race and give wrong results; serialise them (one
+ * stream, or events).  The array keeps the last call's contents. */
+int nurbs_surface_bwd_noalloc(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
+                              const float *ctrl, const float *w, const float *ku,
+                              const float *kv, int nu_s, int nv_s, const float *us,
+                              const float *vs, int uv_shared, const float *grad_pts,
+                              float *grad_ctrl, float *grad_w, float *grad_ku,
+                              float *grad_kv, unsigned grad_mask, void *stream);
+
 /* ------------------------------------------------------------------------
  * Curves: B rational B-spline curves of one shape in the plane (dim 2) or in
  * space (dim 3),

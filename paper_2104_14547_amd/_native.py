@@ -42,6 +42,7 @@ EXPORTS = (
     "nurbs_plan_set_timing", "nurbs_plan_read_timing",
     "nurbs_find_spans", "nurbs_basis", "nurbs_read_device_error",
     "nurbs_curve_ws_bytes", "nurbs_curve_fwd", "nurbs_curve_bwd",
+    "nurbs_surface_bwd_noalloc",
 )
 
 
@@ -88,6 +89,8 @@ _SIGS = {
     "nurbs_find_spans": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp]),
     "nurbs_basis": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp]),
     "nurbs_read_device_error": (_i, [_vp, _vp, _ip]),
+    "nurbs_surface_bwd_noalloc": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _i, _vp,
+                                       _vp, _vp, _vp, _vp, _u, _vp]),
     "nurbs_curve_ws_bytes": (_i, [_vp, _i, _i, _i, _i, _i, _u, _szp]),
     "nurbs_curve_fwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _sz, _vp]),
     "nurbs_curve_bwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _u, _vp, _sz,

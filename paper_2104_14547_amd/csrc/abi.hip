@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <queue>
 #include <string>
@@ -348,6 +349,73 @@ int nurbs_surface_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, c
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "launch backward");
     return NURBS_OK;
+}
+
+// --------------------------------------------------------------------------
+// uniform backward without a caller workspace
+// --------------------------------------------------------------------------
+namespace {
+
+// Device-resident scratch for nurbs_surface_bwd_noalloc: the backward's
+// tile slots (and the 256-byte header) live here instead of in a caller
+// workspace.  Every device the library runs on holds one copy until the
+// process ends.  Host code must never pass `scratch` itself to a kernel
+// (in host code it is a stand-in, not a device address): it uses the
+// per-device address from hipGetSymbolAddress below.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// The device address of this device's copy of `scratch`, looked up once per
+// device with that device current.
+int scratch_address(nurbs_ctx* ctx, void** out) {
+    if (ctx->device < 0 || ctx->device >= kMaxDevices) return fail(ctx, NURBS_EINVAL, "device ordinal too large");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[ctx->device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipGetDevice");
+        if (cur != ctx->device) return fail(ctx, NURBS_EINVAL, "the context's device is not the current device");
+        void* addr = nullptr;
+        e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipGetSymbolAddress(scratch)");
+        if (!addr) return fail(ctx, NURBS_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_addr[ctx->device] = addr;
+    }
+    *out = g_scratch_addr[ctx->device];
+    return NURBS_OK;
+}
+
+}  // namespace
+
+int nurbs_surface_bwd_noalloc(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, const float* ctrl,
+                              const float* w, const float* ku, const float* kv, int nu_s, int nv_s, const float* us,
+                              const float* vs, int uv_shared, const float* grad_pts, float* grad_ctrl, float* grad_w,
+                              float* grad_ku, float* grad_kv, unsigned grad_mask, void* stream) {
+    int rc = uniform_common(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
+    if (rc) return rc;
+    if (ctx->flags & NURBS_VALIDATE)
+        return fail(ctx, NURBS_EUNSUPPORTED,
+                    "nurbs_surface_bwd_noalloc runs no device-side data checks; clear NURBS_VALIDATE");
+    if (grad_mask & ~NURBS_GRAD_ALL) return fail(ctx, NURBS_EINVAL, "unknown gradient bits");
+    size_t need = 0;
+    rc = nurbs_surface_ws_bytes(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s, grad_mask, &need);
+    if (rc) return rc;
+    if (need > kNoAllocScratchBytes)
+        return fail(ctx, NURBS_EWORKSPACE,
+                    "this backward needs " + std::to_string(need) + " bytes of scratch; the built-in scratch holds " +
+                        std::to_string(kNoAllocScratchBytes) + " (use nurbs_surface_bwd with a workspace)");
+    void* ws = nullptr;
+    rc = scratch_address(ctx, &ws);
+    if (rc) return rc;
+    // same kernels as nurbs_surface_bwd; every slot the finalize reads is
+    // written by the backward kernel of the same call, and no error word is
+    // used (NURBS_VALIDATE is refused), so nothing needs clearing first
+    return nurbs_surface_bwd(ctx, B, p, q, nu_c, nv_c, ctrl, w, ku, kv, nu_s, nv_s, us, vs, uv_shared, grad_pts,
+                             grad_ctrl, grad_w, grad_ku, grad_kv, grad_mask, ws, kNoAllocScratchBytes, stream);
 }
 
 // --------------------------------------------------------------------------
