@@ -243,6 +243,166 @@ def uniform_leg(steps: int):
             "parity": par}
 
 
+VALU_PEAK_INSTR = 256 * 4 * 16 * 2.4e9  # lane-instructions/s: 256 CUs x 4 SIMD16 x 2.4 GHz (no packed FP32)
+
+
+def _ev(torch):
+    return torch.cuda.Event(enable_timing=True)
+
+
+def curve_leg(steps: int):
+    """16384 cubic space curves, 32 control points, 1024 shared samples each,
+    through nurbs_curve_fwd / nurbs_curve_bwd (points, weights and knots):
+    per-call HIP events on the launch stream, the MALL flushed before each
+    step outside the events; parity of the timed outputs on 64 curves."""
+    import torch
+    from paper_2104_14547_amd import _native as N
+    from paper_2104_14547_amd import api
+    from paper_2104_14547_amd import workloads as W
+    from oracle import oracle as O
+    cb = W.curve_batch(seed=8, B=16384, p=3, nc=32, ns=1024, dim=3)
+    dev = torch.device("cuda", 0)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctrl, w, kn, us, g = T(cb.ctrl), T(cb.w), T(cb.knots), T(cb.us), T(cb.upstream)
+    B, p, nc, ns, dim = cb.B, cb.p, cb.nc, cb.ns, cb.dim
+    ctx = api.context(0)
+    pts = torch.empty((B, ns, dim), dtype=torch.float32, device=dev)
+    gc, gw, gk = torch.empty_like(ctrl), torch.empty_like(w), torch.empty_like(kn)
+    ws_n = __import__("ctypes").c_size_t()
+    api._check(N.lib().nurbs_curve_ws_bytes(ctx.handle, B, p, nc, dim, ns, 7, __import__("ctypes").byref(ws_n)))
+    ws = torch.empty(max(ws_n.value, 256), dtype=torch.uint8, device=dev)
+    st = torch.cuda.current_stream().cuda_stream
+
+    def fwd():
+        api._check(N.lib().nurbs_curve_fwd(ctx.handle, B, p, nc, dim, ctrl.data_ptr(), w.data_ptr(), kn.data_ptr(), ns,
+                                           us.data_ptr(), 1, pts.data_ptr(), None, None, 0, st), ctx.handle)
+
+    def bwd():
+        api._check(N.lib().nurbs_curve_bwd(ctx.handle, B, p, nc, dim, ctrl.data_ptr(), w.data_ptr(), kn.data_ptr(), ns,
+                                           us.data_ptr(), 1, g.data_ptr(), gc.data_ptr(), gw.data_ptr(), gk.data_ptr(),
+                                           7, ws.data_ptr(), ws.numel(), st), ctx.handle)
+
+    for _ in range(3):
+        fwd()
+        bwd()
+    flush = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
+    ev = [(_ev(torch), _ev(torch), _ev(torch)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b, c in ev:
+        flush.fill_(0.0)
+        a.record()
+        fwd()
+        b.record()
+        bwd()
+        c.record()
+    torch.cuda.synchronize()
+    del flush
+    tf = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    tb = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    npts, nU = B * ns, nc + p + 1
+    per_curve = 4 * (dim + 1) * nc + 4 * nU  # control points + weights, knots
+    bytes_fwd = 4 * dim * npts + B * per_curve + 4 * ns
+    bytes_bwd = 4 * dim * npts + 2 * B * per_curve + 4 * ns
+    # parity of the timed outputs on 64 curves
+    sel = np.arange(0, B, B // 64)
+    sub = W.CurveBatch(name="sub", p=p, nc=nc, ns=ns, dim=dim, ctrl=cb.ctrl[sel], w=cb.w[sel], knots=cb.knots[sel],
+                       us=cb.us, upstream=cb.upstream[sel])
+
+    class _P:
+        shapes = np.array([[p, nc, ns, dim]] * len(sel), np.int32)
+        offsets = np.array([[c * nc * dim, c * nc, c * nU, c * ns, c * ns * dim] for c in range(len(sel))], np.int64)
+        ctrl, w, knots = sub.ctrl.ravel(), sub.w.ravel(), sub.knots.ravel()
+        us = np.broadcast_to(sub.us, (len(sel), ns)).ravel()
+    S_or = O.curve_fwd(_P).reshape(len(sel), ns, dim)
+    G_or = O.curve_bwd(_P, sub.upstream.astype(np.float64).ravel())
+    got = pts.cpu().numpy()[sel].astype(np.float64)
+    diag = np.linalg.norm(S_or.max(1) - S_or.min(1), axis=1)
+    perr = float((np.linalg.norm(got - S_or, axis=2).max(1) / diag).max())
+    gerr = 0.0
+    for t, ref in zip((gc, gw, gk), G_or):
+        a = t.cpu().numpy()[sel].reshape(len(sel), -1).astype(np.float64)
+        r = ref.reshape(len(sel), -1)
+        gerr = max(gerr, float((np.abs(a - r).max(1) / np.abs(r).max(1)).max()))
+    ok = perr <= 1e-5 and gerr <= 1e-4
+    dom, t_dom, b_dom = ("k_curve_bwd", tb, bytes_bwd) if tb >= tf else ("k_curve_fwd", tf, bytes_fwd)
+    ach = b_dom / (t_dom * 1e-3) / 1e9
+    return {"workload": cb.name, "api": "nurbs_curve_fwd / nurbs_curve_bwd (CTRL|W|KU)", "points": npts,
+            "steps": steps, "fwd_ms": tf, "bwd_ms": tb,
+            "pts_per_s": npts / ((tf + tb) * 1e-3) if ok else None,
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes": b_dom},
+            "fwd_GBs": bytes_fwd / (tf * 1e-3) / 1e9, "bwd_GBs": bytes_bwd / (tb * 1e-3) / 1e9,
+            "parity": {"curves": int(len(sel)), "max_point_err_rel_bbox": perr, "max_grad_err_rel_inf": gerr,
+                       "pass": ok}}
+
+
+def chamfer_leg(steps: int):
+    """Chamfer and Hausdorff distances and their gradients between 16384
+    evaluated points and a 16384-point target cloud (nurbs_chamfer), and the
+    brute-force nearest-neighbour search alone (nurbs_nearest), with HIP
+    events on the launch stream; parity against the oracle on the timed
+    outputs."""
+    import ctypes
+    import torch
+    from paper_2104_14547_amd import _native as N
+    from paper_2104_14547_amd import api
+    from paper_2104_14547_amd import workloads as W
+    from oracle import oracle as O
+    n = m = 16384
+    P, Q = W.point_sets(seed=6, B=1, n=n, m=m, dim=3)
+    dev = torch.device("cuda", 0)
+    Pt, Qt = (torch.from_numpy(x).to(dev) for x in (P, Q))
+    ctx = api.context(0)
+    ws_n = ctypes.c_size_t()
+    api._check(N.lib().nurbs_chamfer_ws_bytes(ctx.handle, 1, n, m, ctypes.byref(ws_n)))
+    ws = torch.empty(ws_n.value, dtype=torch.uint8, device=dev)
+    out = torch.empty(2, dtype=torch.float32, device=dev)
+    gcd, ghd = torch.empty_like(Pt), torch.empty_like(Pt)
+    idx = torch.empty(n, dtype=torch.int32, device=dev)
+    d2 = torch.empty(n, dtype=torch.float32, device=dev)
+    st = torch.cuda.current_stream().cuda_stream
+
+    def full():
+        api._check(N.lib().nurbs_chamfer(ctx.handle, 1, 3, Pt.data_ptr(), n, Qt.data_ptr(), m, out.data_ptr(),
+                                         gcd.data_ptr(), ghd.data_ptr(), ws.data_ptr(), ws.numel(), st), ctx.handle)
+
+    def nn():
+        api._check(N.lib().nurbs_nearest(ctx.handle, 1, 3, Pt.data_ptr(), n, Qt.data_ptr(), m, idx.data_ptr(),
+                                         d2.data_ptr(), ws.data_ptr(), ws.numel(), st), ctx.handle)
+
+    for _ in range(2):
+        full()
+        nn()
+    ev = [(_ev(torch), _ev(torch), _ev(torch)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b, c in ev:
+        a.record()
+        full()
+        b.record()
+        nn()
+        c.record()
+    torch.cuda.synchronize()
+    t_full = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    t_nn = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    cd, hd, rg_cd, rg_hd = O.chamfer_hausdorff(P[0], Q[0])
+    ri, rd = O.nearest(P[0], Q[0])
+    o = out.cpu().numpy().astype(np.float64)
+    gerr = max(float(np.abs(gcd.cpu().numpy() - rg_cd).max() / np.abs(rg_cd).max()),
+               float(np.abs(ghd.cpu().numpy() - rg_hd).max() / np.abs(rg_hd).max()))
+    nn_exact = bool((idx.cpu().numpy() == ri).all() and (d2.cpu().numpy() == rd).all())
+    ok = nn_exact and abs(o[0] - cd) <= 1e-5 * cd and abs(o[1] - hd) <= 1e-5 * hd and gerr <= 1e-4
+    instr = 9  # per pair: 3 sub, 1 mul, 2 fma, 1 compare, 2 selects
+    ach = n * m * instr / (t_nn * 1e-3)
+    return {"workload": f"chamfer_hausdorff_{n}x{m}_3d", "api": "nurbs_chamfer (CD, HD, both gradients); nurbs_nearest",
+            "pairs_per_nearest": n * m, "steps": steps, "chamfer_ms": t_full, "nearest_ms": t_nn,
+            "pair_evals_per_s": 2 * n * m / (t_full * 1e-3) if ok else None,
+            "roofline": {"bound": "alu", "kernel": "k_nn", "achieved": ach / 1e12, "peak": VALU_PEAK_INSTR / 1e12,
+                         "unit": "T lane-instr/s", "frac": ach / VALU_PEAK_INSTR,
+                         "instr_per_pair": instr},
+            "parity": {"nearest_bit_exact": nn_exact, "cd_rel_err": abs(o[0] - cd) / cd,
+                       "hd_rel_err": abs(o[1] - hd) / hd, "max_grad_err_rel_inf": gerr, "pass": ok}}
+
+
 def fit_leg(steps: int):
     """The fitting loop (64x64 bicubic net, 512x512 samples of
     z = sin 3x cos 3y, Adam lr 1e-2 on points, weights and knots), one HIP
@@ -299,6 +459,8 @@ def main():
     ap.add_argument("--fit-steps", type=int, default=500, help="steps of the fitting leg (0: skip it)")
     ap.add_argument("--uniform-steps", type=int, default=20,
                     help="steps of the 256-surface bicubic uniform-batch leg (0: skip it)")
+    ap.add_argument("--curve-steps", type=int, default=20, help="steps of the curve leg (0: skip it)")
+    ap.add_argument("--chamfer-steps", type=int, default=10, help="steps of the Chamfer/Hausdorff leg (0: skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (scale for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -425,6 +587,14 @@ def main():
         t1 = time.perf_counter()
         result["batch_bicubic"] = uniform_leg(args.uniform_steps)
         log(f"[bench] batch_bicubic {result['batch_bicubic']} ({time.perf_counter() - t1:.1f} s)")
+    if args.curve_steps > 0:
+        t1 = time.perf_counter()
+        result["curves"] = curve_leg(args.curve_steps)
+        log(f"[bench] curves {result['curves']} ({time.perf_counter() - t1:.1f} s)")
+    if args.chamfer_steps > 0:
+        t1 = time.perf_counter()
+        result["chamfer"] = chamfer_leg(args.chamfer_steps)
+        log(f"[bench] chamfer {result['chamfer']} ({time.perf_counter() - t1:.1f} s)")
     if args.fit_steps > 0:
         t1 = time.perf_counter()
         result["fit"] = fit_leg(args.fit_steps)

@@ -241,6 +241,44 @@ int nurbs_curve_bwd(nurbs_ctx *ctx, int B, int p, int nc, int dim, const float *
                     size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Point-set losses: the Chamfer and Hausdorff distances of Sec. 4
+ * (eqs. ChamferDistance and HausdorffDistance), two-sided, with the
+ * Euclidean norm, between evaluated points P and a target set Q, for B
+ * pairs of sets of equal sizes:
+ *     CD = sum_i min_j |P_i - Q_j| + sum_j min_i |P_i - Q_j|
+ *     HD = max_i min_j |P_i - Q_j| + max_j min_i |P_i - Q_j|
+ *   P [B][n][dim], Q [B][m][dim] (dim 2 or 3), n, m >= 1, m <= 2^22.
+ * Nearest and farthest points are integer decisions taken in float32 on
+ * the float32 inputs with d2 = fma(dz, dz, fma(dy, dy, dx * dx)) (dz = 0
+ * in the plane): the smallest d2 wins with the first index on ties, the
+ * largest d2 wins with the first index on ties.  Squared distances must be
+ * finite.  Distances and sums are then FP64, returned as float32.
+ * Workspace: nurbs_chamfer_ws_bytes (covers both calls below).
+ * ---------------------------------------------------------------------- */
+int nurbs_chamfer_ws_bytes(nurbs_ctx *ctx, int B, int n, int m, size_t *out);
+
+/* For each X[b][i] the index idx[b][i] of its nearest point in Y[b] and
+ * that squared distance d2[b][i] (int32 and float32, device arrays
+ * [B][n]).  Brute force over all pairs.  ws: at least the size that
+ * nurbs_chamfer_ws_bytes(ctx, B, n, m) reports (small query sets split the
+ * target set over several workgroups and keep per-range partials there);
+ * NURBS_EWORKSPACE otherwise. */
+int nurbs_nearest(nurbs_ctx *ctx, int B, int dim, const float *X, int n, const float *Y,
+                  int m, int32_t *idx, float *d2, void *ws, size_t ws_bytes, void *stream);
+
+/* out [B][2] = (CD, HD) per pair (device); grad_cd, grad_hd [B][n][dim]:
+ * their gradients with respect to P (either may be NULL):
+ *   dCD/dP_i = u(P_i, Q_a(i)) + sum over j with b(j) = i of u(P_i, Q_j)
+ *   dHD/dP_i = [i = i*] u(P_i, Q_a(i)) + [i = b(j*)] u(P_i, Q_j*)
+ * with u(x, y) = (x - y)/|x - y| (0 when x = y), a / b the nearest maps
+ * and i*, j* the farthest points of P and Q.  Bitwise reproducible: the
+ * sum over the targets that chose a point is kept in 2^-40 fixed point with
+ * 64-bit integer adds (exact, order-independent); no float atomics. */
+int nurbs_chamfer(nurbs_ctx *ctx, int B, int dim, const float *P, int n, const float *Q,
+                  int m, float *out, float *grad_cd, float *grad_hd, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Ragged batch ("plan"): thousands of surfaces of uneven degree, control
  * grid and sample grid in one persistent launch per direction (the paper's
  * batched forward of Alg. Forward over all surfaces, and Alg. Backward).

@@ -43,6 +43,7 @@ EXPORTS = (
     "nurbs_find_spans", "nurbs_basis", "nurbs_read_device_error",
     "nurbs_curve_ws_bytes", "nurbs_curve_fwd", "nurbs_curve_bwd",
     "nurbs_surface_bwd_noalloc",
+    "nurbs_chamfer_ws_bytes", "nurbs_nearest", "nurbs_chamfer",
 )
 
 
@@ -91,6 +92,9 @@ _SIGS = {
     "nurbs_read_device_error": (_i, [_vp, _vp, _ip]),
     "nurbs_surface_bwd_noalloc": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _i, _vp,
                                        _vp, _vp, _vp, _vp, _u, _vp]),
+    "nurbs_chamfer_ws_bytes": (_i, [_vp, _i, _i, _i, _szp]),
+    "nurbs_nearest": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp, _vp, _sz, _vp]),
+    "nurbs_chamfer": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
     "nurbs_curve_ws_bytes": (_i, [_vp, _i, _i, _i, _i, _i, _u, _szp]),
     "nurbs_curve_fwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _sz, _vp]),
     "nurbs_curve_bwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _u, _vp, _sz,

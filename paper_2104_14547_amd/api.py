@@ -317,7 +317,9 @@ def curve_bwd(ctrl, w, knots, p: int, us, grad_pts, mask: int = N.NURBS_GRAD_CTR
     ws_n = ctypes.c_size_t()
     _check(N.lib().nurbs_curve_ws_bytes(ctx.handle, B, int(p), nc, dim, ns, int(mask), ctypes.byref(ws_n)),
            ctx.handle)
-    ws = torch.zeros(ws_n.value, dtype=torch.uint8, device=dev) if ws_n.value else None
+    ws = torch.empty(ws_n.value, dtype=torch.uint8, device=dev) if ws_n.value else None
+    if ws is not None and ctx.validate:
+        ws[:256].zero_()
     ctx.last_ws = ws
     _check(N.lib().nurbs_curve_bwd(ctx.handle, B, int(p), nc, dim, _ptr(ctrl), _ptr(w), _ptr(knots), ns, _ptr(us),
                                    shared, _ptr(grad_pts), _ptr(gc), _ptr(gw), _ptr(gk), int(mask), _ptr(ws),
@@ -353,6 +355,80 @@ class NurbsCurveFn(torch.autograd.Function):
 def curve(ctrl, w, knots, p: int, us):
     """C = curve(ctrl, w, knots, p, us), differentiable in ctrl, w and knots."""
     return NurbsCurveFn.apply(ctrl.contiguous(), w.contiguous(), knots.contiguous(), int(p), us.contiguous())
+
+
+# --------------------------------------------------------------------------
+# point-set losses
+# --------------------------------------------------------------------------
+
+def _sets(P, Q):
+    _need_cuda_f32("P", P)
+    _need_cuda_f32("Q", Q)
+    squeeze = P.dim() == 2
+    if squeeze:
+        P, Q = P[None], Q[None]
+    if P.dim() != 3 or Q.dim() != 3 or P.shape[0] != Q.shape[0] or P.shape[2] != Q.shape[2] or \
+            P.shape[2] not in (2, 3):
+        raise ValueError("P, Q must be [B, n, dim] and [B, m, dim] (or [n, dim], [m, dim]) with dim 2 or 3")
+    return P, Q, int(P.shape[0]), int(P.shape[1]), int(Q.shape[1]), int(P.shape[2]), squeeze
+
+
+def _cd_ws(ctx, B, n, m, dev):
+    ws_n = ctypes.c_size_t()
+    _check(N.lib().nurbs_chamfer_ws_bytes(ctx.handle, B, n, m, ctypes.byref(ws_n)), ctx.handle)
+    return torch.empty(ws_n.value, dtype=torch.uint8, device=dev)
+
+
+def nearest(X, Y, ctx: Context | None = None):
+    """(idx [B, n] int32, d2 [B, n]) of each X point's nearest Y point (nurbs_nearest)."""
+    X, Y, B, n, m, dim, squeeze = _sets(X, Y)
+    ctx = ctx or context(X.device.index)
+    idx = torch.empty((B, n), dtype=torch.int32, device=X.device)
+    d2 = torch.empty((B, n), dtype=torch.float32, device=X.device)
+    ws = _cd_ws(ctx, B, n, m, X.device)
+    _check(N.lib().nurbs_nearest(ctx.handle, B, dim, _ptr(X), n, _ptr(Y), m, _ptr(idx), _ptr(d2), _ptr(ws),
+                                 ws.numel(), _stream(X.device)), ctx.handle)
+    return (idx[0], d2[0]) if squeeze else (idx, d2)
+
+
+def chamfer_hausdorff(P, Q, grads: bool = True, ctx: Context | None = None):
+    """(CD [B], HD [B], dCD/dP, dHD/dP) of point sets (nurbs_chamfer)."""
+    P, Q, B, n, m, dim, squeeze = _sets(P, Q)
+    ctx = ctx or context(P.device.index)
+    out = torch.empty((B, 2), dtype=torch.float32, device=P.device)
+    gcd = torch.empty_like(P) if grads else None
+    ghd = torch.empty_like(P) if grads else None
+    ws = _cd_ws(ctx, B, n, m, P.device)
+    _check(N.lib().nurbs_chamfer(ctx.handle, B, dim, _ptr(P), n, _ptr(Q), m, _ptr(out), _ptr(gcd), _ptr(ghd),
+                                 _ptr(ws), ws.numel(), _stream(P.device)), ctx.handle)
+    cd, hd = out[:, 0], out[:, 1]
+    if squeeze:
+        return cd[0], hd[0], (None if gcd is None else gcd[0]), (None if ghd is None else ghd[0])
+    return cd, hd, gcd, ghd
+
+
+class ChamferFn(torch.autograd.Function):
+    """CD(P, Q) as a differentiable loss in P (the target Q gets no gradient)."""
+
+    @staticmethod
+    def forward(fctx, P, Q, which):
+        cd, hd, gcd, ghd = chamfer_hausdorff(P, Q, grads=True)
+        fctx.save_for_backward(gcd if which == "chamfer" else ghd)
+        return cd if which == "chamfer" else hd
+
+    @staticmethod
+    def backward(fctx, g):
+        (gp,) = fctx.saved_tensors
+        scale = g.reshape(g.shape + (1,) * (gp.dim() - g.dim()))
+        return gp * scale, None, None
+
+
+def chamfer_loss(P, Q):
+    return ChamferFn.apply(P.contiguous(), Q.contiguous(), "chamfer")
+
+
+def hausdorff_loss(P, Q):
+    return ChamferFn.apply(P.contiguous(), Q.contiguous(), "hausdorff")
 
 
 # --------------------------------------------------------------------------

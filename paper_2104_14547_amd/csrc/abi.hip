@@ -513,6 +513,95 @@ int nurbs_curve_bwd(nurbs_ctx* ctx, int B, int p, int nc, int dim, const float* 
 }
 
 // --------------------------------------------------------------------------
+// point-set losses
+// --------------------------------------------------------------------------
+namespace {
+
+struct CdLayout {
+    size_t a, da, b, db, state, part, acc, pidx, pd2, total;
+};
+
+// Workspace of nurbs_nearest / nurbs_chamfer: the 256-byte header, both
+// nearest-neighbour maps, the per-pair state and the per-range partials of
+// the larger of the two searches.
+CdLayout cd_layout(int B, int n, int m, int num_cus) {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const NnSplit s1 = nn_split(B, n, m, num_cus), s2 = nn_split(B, m, n, num_cus);
+    const size_t part = std::max(s1.nranges > 1 ? (size_t)s1.nranges * n : 0, s2.nranges > 1 ? (size_t)s2.nranges * m : 0);
+    CdLayout l;
+    l.a = kWsHeader;
+    l.da = l.a + al(sizeof(int) * (size_t)B * n);
+    l.b = l.da + al(sizeof(float) * (size_t)B * n);
+    l.db = l.b + al(sizeof(int) * (size_t)B * m);
+    l.state = l.db + al(sizeof(float) * (size_t)B * m);
+    l.part = l.state + al(cd_state_bytes() * (size_t)B);
+    l.acc = l.part + al(cd_part_bytes(n, m) * (size_t)B);
+    l.pidx = l.acc + al(sizeof(unsigned long long) * 3 * (size_t)B * n);
+    l.pd2 = l.pidx + al(sizeof(int) * (size_t)B * part);
+    l.total = l.pd2 + al(sizeof(float) * (size_t)B * part);
+    return l;
+}
+
+int cd_common(nurbs_ctx* ctx, int B, int dim, int n, int m) {
+    if (!ctx) return fail(nullptr, NURBS_EINVAL, "ctx is NULL");
+    if (dim != 2 && dim != 3) return fail(ctx, NURBS_EINVAL, "dim must be 2 or 3");
+    if (B < 0 || n < 1 || m < 1) return fail(ctx, NURBS_EINVAL, "need B >= 0 and at least one point in each set");
+    if ((long long)B * n > (1ll << 30) || (long long)B * m > (1ll << 30) || B > 65535 || m > (1 << 22))
+        return fail(ctx, NURBS_EINVAL, "point sets too large");
+    return NURBS_OK;
+}
+
+}  // namespace
+
+int nurbs_chamfer_ws_bytes(nurbs_ctx* ctx, int B, int n, int m, size_t* out) {
+    int rc = cd_common(ctx, B, 3, n, m);
+    if (rc) return rc;
+    if (!out) return fail(ctx, NURBS_EINVAL, "out is NULL");
+    *out = cd_layout(B, n, m, ctx->num_cus).total;
+    return NURBS_OK;
+}
+
+int nurbs_nearest(nurbs_ctx* ctx, int B, int dim, const float* X, int n, const float* Y, int m, int32_t* idx,
+                  float* d2, void* ws, size_t ws_bytes, void* stream) {
+    int rc = cd_common(ctx, B, dim, n, m);
+    if (rc) return rc;
+    if (B == 0) return NURBS_OK;
+    if (!X || !Y || !idx || !d2) return fail(ctx, NURBS_EINVAL, "NULL array");
+    const CdLayout l = cd_layout(B, n, m, ctx->num_cus);
+    const NnSplit sp = nn_split(B, n, m, ctx->num_cus);
+    char* w = reinterpret_cast<char*>(ws);
+    if (!ws || ws_bytes < l.total)
+        return fail(ctx, NURBS_EWORKSPACE, "workspace too small: need " + std::to_string(l.total));
+    hipError_t e = launch_nn(dim, reinterpret_cast<hipStream_t>(stream), B, X, n, Y, m, sp, idx, d2,
+                             sp.nranges > 1 ? reinterpret_cast<int*>(w + l.pidx) : nullptr,
+                             sp.nranges > 1 ? reinterpret_cast<float*>(w + l.pd2) : nullptr);
+    return e ? hip_fail(ctx, e, "launch nearest") : NURBS_OK;
+}
+
+int nurbs_chamfer(nurbs_ctx* ctx, int B, int dim, const float* P, int n, const float* Q, int m, float* out,
+                  float* grad_cd, float* grad_hd, void* ws, size_t ws_bytes, void* stream) {
+    int rc = cd_common(ctx, B, dim, n, m);
+    if (rc) return rc;
+    if (B == 0) return NURBS_OK;
+    if (!P || !Q || !out) return fail(ctx, NURBS_EINVAL, "NULL array");
+    const CdLayout l = cd_layout(B, n, m, ctx->num_cus);
+    if (!ws || ws_bytes < l.total) return fail(ctx, NURBS_EWORKSPACE, "workspace too small: need " + std::to_string(l.total));
+    char* w = reinterpret_cast<char*>(ws);
+    int* a = reinterpret_cast<int*>(w + l.a);
+    float* da = reinterpret_cast<float*>(w + l.da);
+    int* bq = reinterpret_cast<int*>(w + l.b);
+    float* db = reinterpret_cast<float*>(w + l.db);
+    int* pidx = reinterpret_cast<int*>(w + l.pidx);
+    float* pd2 = reinterpret_cast<float*>(w + l.pd2);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = launch_nn(dim, st, B, P, n, Q, m, nn_split(B, n, m, ctx->num_cus), a, da, pidx, pd2);
+    if (e == hipSuccess) e = launch_nn(dim, st, B, Q, m, P, n, nn_split(B, m, n, ctx->num_cus), bq, db, pidx, pd2);
+    if (e == hipSuccess)
+        e = launch_cd(dim, st, B, P, n, Q, m, a, da, bq, db, out, w + l.state, w + l.part, w + l.acc, grad_cd, grad_hd);
+    return e ? hip_fail(ctx, e, "launch chamfer") : NURBS_OK;
+}
+
+// --------------------------------------------------------------------------
 // plans
 // --------------------------------------------------------------------------
 namespace {

@@ -20,15 +20,16 @@
 // and control polygon in LDS.  A wave handles 64 consecutive samples at a
 // time, one per lane.  Backward contributions are reduced without atomics:
 // when the 64 spans of a wave are non-decreasing (sorted parameters, the
-// usual case), equal spans form runs of lanes and a segmented scan sums each
-// run, whose last lane adds the sums into the wave's LDS accumulators; an
+// usual case), equal spans form runs of lanes and a DPP segmented scan (the
+// surface backward's, one v_fmac_f32_dpp per value and step) sums each run,
+// whose last lane adds the sums into the wave's LDS accumulators; an
 // unsorted wave adds its lanes one after the other.  At the end of the
 // chunk the four waves' accumulators are added in wave order.  A curve with
 // one chunk writes its gradients directly; longer curves write one partial
 // per chunk to the workspace and a finalize kernel adds the partials in
 // chunk order.  Every sum has a fixed order, so results are bitwise
 // reproducible.
-#include "device.hpp"
+#include "kernels.hpp"
 #include "launch.hpp"
 #include "../../include/nurbsdiff.h"
 
@@ -129,17 +130,6 @@ __global__ void __launch_bounds__(kWG) k_curve_fwd(CurveArgs a, float* __restric
 // backward
 // --------------------------------------------------------------------------
 
-// Segmented inclusive scan across the wave: lane l ends with the sum of the
-// values of lanes start..l (its run so far), in a fixed order.
-__device__ __forceinline__ float seg_scan(float v, int lane, int start) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const float y = __shfl_up(v, d);
-        if (lane - d >= start) v += y;
-    }
-    return v;
-}
-
 // per-wave accumulators: control point i -> (dL/dP_i xyz, dL/dw_i); knot t -> dL/dU_t
 struct CurveAcc {
     float4 cp[kWG];
@@ -174,14 +164,12 @@ __global__ void __launch_bounds__(kWG) k_curve_bwd(CurveArgs a, const float* __r
     for (int base = b.s0 + wv * kWave; base < b.s1; base += kWG) {
         const int s = base + lane;
         const bool act = s < b.s1;
-        float cP[P + 1][DIM], cW[P + 1], gU[2 * P + 2];
+        // per control point r of the sample's span: (dL/dP xyz, dL/dw)
+        float4 c4[P + 1];
+        float gU[2 * P + 2];
         int k = kSentinel;
 #pragma unroll
-        for (int r = 0; r <= P; ++r) {
-            cW[r] = 0.f;
-#pragma unroll
-            for (int x = 0; x < DIM; ++x) cP[r][x] = 0.f;
-        }
+        for (int r = 0; r <= P; ++r) c4[r] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int t = 0; t < 2 * P + 2; ++t) gU[t] = 0.f;
         if (act) {
@@ -202,7 +190,8 @@ __global__ void __launch_bounds__(kWG) k_curve_bwd(CurveArgs a, const float* __r
             const float inv = recip(Wsum);
 #pragma unroll
             for (int x2 = 0; x2 < DIM; ++x2) C[x2] *= inv;
-            float g[3] = {g0[(size_t)s * DIM], g0[(size_t)s * DIM + 1], DIM == 3 ? g0[(size_t)s * DIM + 2] : 0.f};
+            const float g[3] = {g0[(size_t)s * DIM], g0[(size_t)s * DIM + 1],
+                                DIM == 3 ? g0[(size_t)s * DIM + 2] : 0.f};
             float e[P + 1];
 #pragma unroll
             for (int r = 0; r <= P; ++r) {
@@ -211,9 +200,7 @@ __global__ void __launch_bounds__(kWG) k_curve_bwd(CurveArgs a, const float* __r
                 pg = __builtin_fmaf(q.y - C[1], g[1], pg);
                 if constexpr (DIM == 3) pg = __builtin_fmaf(q.z - C[2], g[2], pg);
                 const float nw = N[r] * q.w * inv;
-#pragma unroll
-                for (int x2 = 0; x2 < DIM; ++x2) cP[r][x2] = nw * g[x2];
-                cW[r] = N[r] * pg * inv;
+                c4[r] = make_float4(nw * g[0], nw * g[1], nw * g[2], N[r] * pg * inv);
                 e[r] = q.w * pg * inv;
             }
             if (want_k) basis_knot_adjoint<P>(U, k, x, e, gU);
@@ -221,32 +208,27 @@ __global__ void __launch_bounds__(kWG) k_curve_bwd(CurveArgs a, const float* __r
         // spans non-decreasing across the wave?
         int kprev = __shfl_up(k, 1);
         if (lane == 0) kprev = k;
-        const unsigned long long head = __ballot(lane == 0 || k != kprev);
         const bool sorted = __ballot(k < kprev) == 0ull;
         if (sorted) {
-            const int start = 63 - __clzll(head & (~0ull >> (63 - lane)));
-            const bool last = lane == kWave - 1 || (((head >> lane) >> 1) & 1ull);
+            // runs of equal spans: DPP segmented scans, then the last lane of
+            // each run adds the run's sums; for a fixed r the run ends touch
+            // distinct control points
+            const Runs rn = wave_runs(k);
 #pragma unroll
-            for (int r = 0; r <= P; ++r) {
-#pragma unroll
-                for (int x2 = 0; x2 < DIM; ++x2) cP[r][x2] = seg_scan(cP[r][x2], lane, start);
-                cW[r] = seg_scan(cW[r], lane, start);
-            }
+            for (int r = 0; r <= P; ++r) seg_scan4(c4[r], rn);
             if (want_k) {
 #pragma unroll
-                for (int t = 0; t < 2 * P + 2; ++t) gU[t] = seg_scan(gU[t], lane, start);
+                for (int t = 0; t < 2 * P + 2; t += 2) seg_scan2(gU[t], gU[t + 1], rn);
             }
-            // one lane per run adds its run's sums; for a fixed r the run ends
-            // touch distinct control points
-            const bool wr = last && k != kSentinel;
+            const bool wr = rn.head && k != kSentinel;
 #pragma unroll
             for (int r = 0; r <= P; ++r) {
                 if (wr) {
                     float4 v = A.cp[k - P + r];
-                    v.x += cP[r][0];
-                    v.y += cP[r][1];
-                    if constexpr (DIM == 3) v.z += cP[r][2];
-                    v.w += cW[r];
+                    v.x += c4[r].x;
+                    v.y += c4[r].y;
+                    if constexpr (DIM == 3) v.z += c4[r].z;
+                    v.w += c4[r].w;
                     A.cp[k - P + r] = v;
                 }
                 wave_lds_sync();
@@ -268,9 +250,9 @@ __global__ void __launch_bounds__(kWG) k_curve_bwd(CurveArgs a, const float* __r
                 float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
                 for (int r = 0; r <= P; ++r) {
-                    const float px = bcast_lane(cP[r][0], l), py = bcast_lane(cP[r][1], l);
-                    const float pz = DIM == 3 ? bcast_lane(cP[r][DIM - 1], l) : 0.f;
-                    const float pw = bcast_lane(cW[r], l);
+                    const float px = bcast_lane(c4[r].x, l), py = bcast_lane(c4[r].y, l);
+                    const float pz = DIM == 3 ? bcast_lane(c4[r].z, l) : 0.f;
+                    const float pw = bcast_lane(c4[r].w, l);
                     if (lane == r) v = make_float4(px, py, pz, pw);
                 }
                 if (lane <= P) {

@@ -105,6 +105,20 @@ hipError_t launch_curve_fwd(int p, int dim, hipStream_t st, const CurveArgs& a, 
 hipError_t launch_curve_bwd(int p, int dim, hipStream_t st, const CurveArgs& a, const float* gpts, float* gctrl,
                             float* gw, float* gk, float* part, unsigned mask);
 
+// point-set losses (k_chamfer.hip)
+struct NnSplit {
+    int nranges;  // target ranges (workgroups along the target set)
+    int range;    // targets per range (a multiple of 256)
+};
+NnSplit nn_split(int B, int n, int m, int num_cus);
+hipError_t launch_nn(int dim, hipStream_t st, int B, const float* X, int n, const float* Y, int m,
+                     const NnSplit& sp, int* idx, float* d2, int* pidx, float* pd2);
+hipError_t launch_cd(int dim, hipStream_t st, int B, const float* P, int n, const float* Q, int m, const int* a,
+                     const float* da, const int* bq, const float* db, float* out, void* state, void* part,
+                     void* acc, float* gcd, float* ghd);
+size_t cd_state_bytes();
+size_t cd_part_bytes(int n, int m);  // per pair
+
 // test exports
 // zero n floats on stream st (a kernel, so graph capture records no memset)
 hipError_t launch_zero(hipStream_t st, float* p, size_t n);

@@ -348,6 +348,33 @@ def curve_batch(seed: int = 5, B: int = 64, p: int = 3, nc: int = 16, ns: int = 
                       ctrl=ctrl.astype(np.float32), w=w.astype(np.float32), knots=knots, us=us, upstream=up)
 
 
+# --------------------------------------------------------------------------
+# point sets for the Chamfer / Hausdorff losses
+# --------------------------------------------------------------------------
+
+def point_sets(seed: int = 6, B: int = 1, n: int = 16384, m: int = 16384, dim: int = 3,
+               lattice: bool = False):
+    """B pairs (P [B][n][dim], Q [B][m][dim]) standing in for evaluated
+    surface points and a scanned target cloud: P on the unit square at
+    uniform random (u, v) with z = 0.2 sin(3u) cos(3v), Q the same surface at
+    other random parameters with U(-0.02, 0.02) noise.  With ``lattice``,
+    both are points of the integer lattice {0..7}^dim scaled by 1/8, so
+    many squared distances tie exactly."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if lattice:
+        P = rng.integers(0, 8, (B, n, dim)) / 8.0
+        Q = rng.integers(0, 8, (B, m, dim)) / 8.0
+        return P.astype(np.float32), Q.astype(np.float32)
+
+    def draw(k, noise):
+        u = rng.uniform(0.0, 1.0, (B, k))
+        v = rng.uniform(0.0, 1.0, (B, k))
+        X = np.stack([u, v, 0.2 * np.sin(3 * u) * np.cos(3 * v)], -1)[..., :dim]
+        return X + rng.uniform(-noise, noise, X.shape)
+
+    return draw(n, 0.0).astype(np.float32), draw(m, 0.02).astype(np.float32)
+
+
 WORKLOADS = {
     "single_bicubic": single_bicubic,
     "batch_bicubic": batch_bicubic,
