@@ -336,6 +336,82 @@ def curve_leg(steps: int):
                        "pass": ok}}
 
 
+def uv_leg(steps: int):
+    """64 bicubic 16x16 surfaces, each evaluated at 65536 scattered (u, v)
+    pairs in random order (nurbs_surface_uv_fwd / nurbs_surface_uv_bwd, all
+    four gradients): HIP events on the launch stream, MALL flushed before each
+    step outside the events; parity on 4 surfaces of the timed outputs."""
+    import ctypes
+    import torch
+    from paper_2104_14547_amd import _native as N
+    from paper_2104_14547_amd import api
+    from paper_2104_14547_amd import workloads as W
+    from oracle import oracle as O
+    ub = W.uv_batch(seed=9, B=64, p=3, q=3, nu_c=16, nv_c=16, npts=65536)
+    dev = torch.device("cuda", 0)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctrl, w, ku, kv, uv, g = T(ub.ctrl), T(ub.w), T(ub.ku), T(ub.kv), T(ub.uv), T(ub.upstream)
+    B, p, q, nc, npts = ub.B, 3, 3, 16, ub.npts
+    ctx = api.context(0)
+    pts = torch.empty((B, npts, 3), dtype=torch.float32, device=dev)
+    gc, gw, gu, gv = (torch.empty_like(x) for x in (ctrl, w, ku, kv))
+    ws_n = ctypes.c_size_t()
+    api._check(N.lib().nurbs_surface_uv_ws_bytes(ctx.handle, B, p, q, nc, nc, npts, 15, ctypes.byref(ws_n)))
+    ws = torch.empty(ws_n.value, dtype=torch.uint8, device=dev)
+    st = torch.cuda.current_stream().cuda_stream
+
+    def fwd():
+        api._check(N.lib().nurbs_surface_uv_fwd(ctx.handle, B, p, q, nc, nc, ctrl.data_ptr(), w.data_ptr(),
+                                                ku.data_ptr(), kv.data_ptr(), npts, uv.data_ptr(), 0,
+                                                pts.data_ptr(), None, None, None, 0, st), ctx.handle)
+
+    def bwd():
+        api._check(N.lib().nurbs_surface_uv_bwd(ctx.handle, B, p, q, nc, nc, ctrl.data_ptr(), w.data_ptr(),
+                                                ku.data_ptr(), kv.data_ptr(), npts, uv.data_ptr(), 0, g.data_ptr(),
+                                                gc.data_ptr(), gw.data_ptr(), gu.data_ptr(), gv.data_ptr(), 15,
+                                                ws.data_ptr(), ws.numel(), st), ctx.handle)
+
+    for _ in range(3):
+        fwd()
+        bwd()
+    flush = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
+    ev = [(_ev(torch), _ev(torch), _ev(torch)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b, c in ev:
+        flush.fill_(0.0)
+        a.record()
+        fwd()
+        b.record()
+        bwd()
+        c.record()
+    torch.cuda.synchronize()
+    del flush
+    tf = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    tb = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    n = B * npts
+    per_surf = 16 * nc * nc + 4 * 2 * (nc + p + 1)
+    bytes_fwd = 20 * n + B * per_surf
+    bytes_bwd = 20 * n + 2 * B * per_surf
+    perr = gerr = 0.0
+    for b in range(0, B, B // 4):
+        S = O.scattered_fwd(ub.ctrl[b], ub.w[b], ub.ku[b], ub.kv[b], p, q, ub.uv[b])
+        diag = np.linalg.norm(S.max(0) - S.min(0))
+        perr = max(perr, float(np.linalg.norm(pts[b].cpu().numpy() - S, axis=1).max() / diag))
+        ref = O.scattered_bwd(ub.ctrl[b], ub.w[b], ub.ku[b], ub.kv[b], p, q, ub.uv[b],
+                              ub.upstream[b].astype(np.float64))
+        for t, r in zip((gc, gw, gu, gv), ref):
+            gerr = max(gerr, float(np.abs(t[b].cpu().numpy().ravel() - r.ravel()).max() / np.abs(r).max()))
+    ok = perr <= 1e-5 and gerr <= 1e-4
+    dom, t_dom, b_dom = ("k_uv_acc+k_uv_max+k_uv_fin", tb, bytes_bwd) if tb >= tf else ("k_uv_fwd", tf, bytes_fwd)
+    ach = b_dom / (t_dom * 1e-3) / 1e9
+    return {"workload": ub.name, "api": "nurbs_surface_uv_fwd / nurbs_surface_uv_bwd (all gradients)", "points": n,
+            "steps": steps, "fwd_ms": tf, "bwd_ms": tb, "pts_per_s": n / ((tf + tb) * 1e-3) if ok else None,
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes": b_dom},
+            "fwd_GBs": bytes_fwd / (tf * 1e-3) / 1e9, "bwd_GBs": bytes_bwd / (tb * 1e-3) / 1e9,
+            "parity": {"surfaces": 4, "max_point_err_rel_bbox": perr, "max_grad_err_rel_inf": gerr, "pass": ok}}
+
+
 def chamfer_leg(steps: int):
     """Chamfer and Hausdorff distances and their gradients between 16384
     evaluated points and a 16384-point target cloud (nurbs_chamfer), and the
@@ -460,6 +536,7 @@ def main():
     ap.add_argument("--uniform-steps", type=int, default=20,
                     help="steps of the 256-surface bicubic uniform-batch leg (0: skip it)")
     ap.add_argument("--curve-steps", type=int, default=20, help="steps of the curve leg (0: skip it)")
+    ap.add_argument("--uv-steps", type=int, default=10, help="steps of the scattered-pair leg (0: skip it)")
     ap.add_argument("--chamfer-steps", type=int, default=10, help="steps of the Chamfer/Hausdorff leg (0: skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (scale for HBM byte counters) and exit")
@@ -591,6 +668,10 @@ def main():
         t1 = time.perf_counter()
         result["curves"] = curve_leg(args.curve_steps)
         log(f"[bench] curves {result['curves']} ({time.perf_counter() - t1:.1f} s)")
+    if args.uv_steps > 0:
+        t1 = time.perf_counter()
+        result["scattered_uv"] = uv_leg(args.uv_steps)
+        log(f"[bench] scattered_uv {result['scattered_uv']} ({time.perf_counter() - t1:.1f} s)")
     if args.chamfer_steps > 0:
         t1 = time.perf_counter()
         result["chamfer"] = chamfer_leg(args.chamfer_steps)

@@ -204,6 +204,45 @@ int nurbs_surface_bwd_noalloc(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int
                               float *grad_kv, unsigned grad_mask, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Surfaces at scattered parameter pairs: eq. NURBS at each (u_k, v_k), in
+ * any order (Sec. 3.1 evaluates the grid of all pairs of two lists; a
+ * point cloud with its own parameters needs single pairs).  B surfaces of
+ * one shape, npts pairs each:
+ *   ctrl [B][nu_c][nv_c][3], w [B][nu_c][nv_c], ku [B][nu_c+p+1],
+ *   kv [B][nv_c+q+1]; uv [npts][2] if uv_shared else [B][npts][2];
+ *   pts, pts_du, pts_dv, grad_pts [B][npts][3].
+ * Shape, knot, weight and parameter rules as for the grids (parameters
+ * clamped into the domain, half-open spans); the pairs need not be sorted.
+ * Workspace: nurbs_surface_uv_ws_bytes (0 for a forward without
+ * NURBS_VALIDATE).
+ * ---------------------------------------------------------------------- */
+int nurbs_surface_uv_ws_bytes(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
+                              int npts, unsigned grad_mask, size_t *out);
+
+/* S at every pair and, for each non-NULL one of pts_du, pts_dv, the
+ * parametric derivatives (Appendix A, eq. NURBSuDerivative1).  At least
+ * one output must be given. */
+int nurbs_surface_uv_fwd(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
+                         const float *ctrl, const float *w, const float *ku,
+                         const float *kv, int npts, const float *uv, int uv_shared,
+                         float *pts, float *pts_du, float *pts_dv, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/* Vector-Jacobian product at the pairs (Sec. 3.2 at each pair); outputs
+ * and grad_mask as nurbs_surface_bwd.  Each gradient entry is a sum over
+ * pairs in arbitrary order, so the terms are added exactly: each is rounded
+ * to a multiple of 2^-s (2^s the largest power of two with npts times the
+ * largest term of that gradient tensor at most 2^62) and summed as 64-bit
+ * integers, which is order-independent (bitwise reproducible, no float
+ * atomics).  The rounding adds at most npts * max|term| * 2^-63 per entry. */
+int nurbs_surface_uv_bwd(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
+                         const float *ctrl, const float *w, const float *ku,
+                         const float *kv, int npts, const float *uv, int uv_shared,
+                         const float *grad_pts, float *grad_ctrl, float *grad_w,
+                         float *grad_ku, float *grad_kv, unsigned grad_mask, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Curves: B rational B-spline curves of one shape in the plane (dim 2) or in
  * space (dim 3),
  *     C(u) = sum_i N_i^p(u) w_i P_i / sum_i N_i^p(u) w_i,

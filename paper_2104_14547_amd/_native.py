@@ -44,6 +44,7 @@ EXPORTS = (
     "nurbs_curve_ws_bytes", "nurbs_curve_fwd", "nurbs_curve_bwd",
     "nurbs_surface_bwd_noalloc",
     "nurbs_chamfer_ws_bytes", "nurbs_nearest", "nurbs_chamfer",
+    "nurbs_surface_uv_ws_bytes", "nurbs_surface_uv_fwd", "nurbs_surface_uv_bwd",
 )
 
 
@@ -92,6 +93,11 @@ _SIGS = {
     "nurbs_read_device_error": (_i, [_vp, _vp, _ip]),
     "nurbs_surface_bwd_noalloc": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _i, _vp,
                                        _vp, _vp, _vp, _vp, _u, _vp]),
+    "nurbs_surface_uv_ws_bytes": (_i, [_vp, _i, _i, _i, _i, _i, _i, _u, _szp]),
+    "nurbs_surface_uv_fwd": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz,
+                                  _vp]),
+    "nurbs_surface_uv_bwd": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp,
+                                  _u, _vp, _sz, _vp]),
     "nurbs_chamfer_ws_bytes": (_i, [_vp, _i, _i, _i, _szp]),
     "nurbs_nearest": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp, _vp, _sz, _vp]),
     "nurbs_chamfer": (_i, [_vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp]),

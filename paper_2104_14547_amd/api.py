@@ -358,6 +358,114 @@ def curve(ctrl, w, knots, p: int, us):
 
 
 # --------------------------------------------------------------------------
+# surfaces at scattered (u, v) pairs
+# --------------------------------------------------------------------------
+
+def _uv_shapes(ctrl, w, ku, kv, p, q, uv):
+    for name, t in (("ctrl", ctrl), ("w", w), ("ku", ku), ("kv", kv), ("uv", uv)):
+        _need_cuda_f32(name, t)
+    if ctrl.dim() == 3:
+        ctrl, w, ku, kv = ctrl[None], w[None], ku[None], kv[None]
+    if ctrl.dim() != 4 or ctrl.shape[-1] != 3:
+        raise ValueError("ctrl must be [B, nu_c, nv_c, 3] or [nu_c, nv_c, 3]")
+    B, nu_c, nv_c = (int(x) for x in ctrl.shape[:3])
+    if tuple(w.shape) != (B, nu_c, nv_c) or tuple(ku.shape) != (B, nu_c + p + 1) or \
+            tuple(kv.shape) != (B, nv_c + q + 1):
+        raise ValueError("w must be [B, nu_c, nv_c], knots [B, nu_c+p+1] and [B, nv_c+q+1]")
+    if uv.dim() == 2 and uv.shape[1] == 2:
+        shared, npts = 1, int(uv.shape[0])
+    elif uv.dim() == 3 and uv.shape[0] == B and uv.shape[2] == 2:
+        shared, npts = 0, int(uv.shape[1])
+    else:
+        raise ValueError("uv must be [npts, 2] (shared) or [B, npts, 2]")
+    return ctrl, w, ku, kv, B, nu_c, nv_c, npts, shared
+
+
+def surface_uv_fwd(ctrl, w, ku, kv, p: int, q: int, uv, derivs: bool = False, ctx: Context | None = None):
+    """S [B, npts, 3] at scattered pairs (nurbs_surface_uv_fwd); with
+    ``derivs`` also (dS/du, dS/dv)."""
+    squeeze = ctrl.dim() == 3
+    ctrl, w, ku, kv, B, nu_c, nv_c, npts, shared = _uv_shapes(ctrl, w, ku, kv, p, q, uv)
+    ctx = ctx or context(ctrl.device.index)
+    dev = ctrl.device
+    pts = torch.empty((B, npts, 3), dtype=torch.float32, device=dev)
+    du = torch.empty_like(pts) if derivs else None
+    dv = torch.empty_like(pts) if derivs else None
+    ws = torch.zeros(256, dtype=torch.uint8, device=dev) if ctx.validate else None
+    ctx.last_ws = ws
+    _check(N.lib().nurbs_surface_uv_fwd(ctx.handle, B, int(p), int(q), nu_c, nv_c, _ptr(ctrl), _ptr(w), _ptr(ku),
+                                        _ptr(kv), npts, _ptr(uv), shared, _ptr(pts), _ptr(du), _ptr(dv), _ptr(ws),
+                                        0 if ws is None else 256, _stream(dev)), ctx.handle)
+    out = (pts, du, dv)
+    if squeeze:
+        out = tuple(None if x is None else x[0] for x in out)
+    return out if derivs else out[0]
+
+
+def surface_uv_bwd(ctrl, w, ku, kv, p: int, q: int, uv, grad_pts, mask: int = N.NURBS_GRAD_ALL,
+                   ctx: Context | None = None):
+    """(dL/dctrl, dL/dw, dL/dku, dL/dkv) at scattered pairs (nurbs_surface_uv_bwd)."""
+    squeeze = ctrl.dim() == 3
+    ctrl, w, ku, kv, B, nu_c, nv_c, npts, shared = _uv_shapes(ctrl, w, ku, kv, p, q, uv)
+    grad_pts = grad_pts.contiguous()
+    if squeeze:
+        grad_pts = grad_pts[None]
+    _need_cuda_f32("grad_pts", grad_pts)
+    if tuple(grad_pts.shape) != (B, npts, 3):
+        raise ValueError("grad_pts must be [B, npts, 3]")
+    ctx = ctx or context(ctrl.device.index)
+    dev = ctrl.device
+    gc = torch.empty_like(ctrl) if mask & N.NURBS_GRAD_CTRL else None
+    gw = torch.empty_like(w) if mask & N.NURBS_GRAD_W else None
+    gu = torch.empty_like(ku) if mask & N.NURBS_GRAD_KU else None
+    gv = torch.empty_like(kv) if mask & N.NURBS_GRAD_KV else None
+    ws_n = ctypes.c_size_t()
+    _check(N.lib().nurbs_surface_uv_ws_bytes(ctx.handle, B, int(p), int(q), nu_c, nv_c, npts, int(mask),
+                                             ctypes.byref(ws_n)), ctx.handle)
+    ws = torch.empty(ws_n.value, dtype=torch.uint8, device=dev) if ws_n.value else None
+    if ws is not None and ctx.validate:
+        ws[:256].zero_()
+    ctx.last_ws = ws
+    _check(N.lib().nurbs_surface_uv_bwd(ctx.handle, B, int(p), int(q), nu_c, nv_c, _ptr(ctrl), _ptr(w), _ptr(ku),
+                                        _ptr(kv), npts, _ptr(uv), shared, _ptr(grad_pts), _ptr(gc), _ptr(gw),
+                                        _ptr(gu), _ptr(gv), int(mask), _ptr(ws), ws_n.value, _stream(dev)),
+           ctx.handle)
+    res = (gc, gw, gu, gv)
+    if squeeze:
+        res = tuple(None if r is None else r[0] for r in res)
+    return res
+
+
+class NurbsSurfaceUVFn(torch.autograd.Function):
+    """Differentiable evaluation at scattered pairs with the library's adjoint."""
+
+    @staticmethod
+    def forward(fctx, ctrl, w, ku, kv, p, q, uv):
+        pts = surface_uv_fwd(ctrl, w, ku, kv, p, q, uv)
+        fctx.save_for_backward(ctrl, w, ku, kv, uv)
+        fctx.pq = (p, q)
+        return pts
+
+    @staticmethod
+    def backward(fctx, grad_pts):
+        ctrl, w, ku, kv, uv = fctx.saved_tensors
+        need = fctx.needs_input_grad
+        mask = (N.NURBS_GRAD_CTRL if need[0] else 0) | (N.NURBS_GRAD_W if need[1] else 0) | \
+               (N.NURBS_GRAD_KU if need[2] else 0) | (N.NURBS_GRAD_KV if need[3] else 0)
+        if mask == 0:
+            return (None,) * 7
+        gc, gw, gu, gv = surface_uv_bwd(ctrl, w, ku, kv, *fctx.pq, uv, grad_pts.contiguous(), mask)
+        return gc, gw, gu, gv, None, None, None
+
+
+def surface_uv(ctrl, w, ku, kv, p: int, q: int, uv):
+    """S = surface(ctrl, w, ku, kv, p, q, uv) at scattered pairs uv [npts, 2],
+    differentiable in ctrl, w, ku and kv."""
+    return NurbsSurfaceUVFn.apply(ctrl.contiguous(), w.contiguous(), ku.contiguous(), kv.contiguous(), int(p),
+                                  int(q), uv.contiguous())
+
+
+# --------------------------------------------------------------------------
 # point-set losses
 # --------------------------------------------------------------------------
 

@@ -513,6 +513,101 @@ int nurbs_curve_bwd(nurbs_ctx* ctx, int B, int p, int nc, int dim, const float* 
 }
 
 // --------------------------------------------------------------------------
+// surfaces at scattered (u, v) pairs
+// --------------------------------------------------------------------------
+namespace {
+
+struct UvLayout {
+    size_t maxbits, acc, total;
+};
+
+UvLayout uv_layout(int B, int p, int q, int nu_c, int nv_c) {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t nacc = 4 * (size_t)nu_c * nv_c + (nu_c + p + 1) + (nv_c + q + 1);
+    UvLayout l;
+    l.maxbits = kWsHeader;
+    l.acc = l.maxbits + al(sizeof(unsigned) * 4 * (size_t)B);
+    l.total = l.acc + al(sizeof(unsigned long long) * nacc * (size_t)B);
+    return l;
+}
+
+int uv_common(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, int npts) {
+    if (!ctx) return fail(nullptr, NURBS_EINVAL, "ctx is NULL");
+    if (B < 0 || npts < 0) return fail(ctx, NURBS_EINVAL, "negative batch or pair count");
+    if (B > 65535) return fail(ctx, NURBS_EINVAL, "batch too large");
+    return check_shape(ctx, p, q, nu_c, nv_c, npts, 1);
+}
+
+UvArgs uv_args(const nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, int npts, const float* ctrl,
+               const float* w, const float* ku, const float* kv, const float* uv, int uv_shared, void* ws) {
+    UvArgs a;
+    a.ctrl = ctrl; a.w = w; a.ku = ku; a.kv = kv; a.uv = uv;
+    a.B = B; a.p = p; a.q = q; a.nu_c = nu_c; a.nv_c = nv_c; a.npts = npts; a.uv_shared = uv_shared ? 1 : 0;
+    a.nacc = 4 * nu_c * nv_c + (nu_c + p + 1) + (nv_c + q + 1);
+    a.lds_acc = a.nacc <= kUvLdsAccMax ? 1 : 0;
+    // pairs per backward workgroup: about 2048 workgroups over the batch;
+    // with LDS accumulators at least 1024 pairs, so that the one flush of a
+    // workgroup's accumulators stays small against its pairs
+    const long long total = (long long)B * npts;
+    long long c = ((total + 2047) / 2048 + 255) / 256 * 256;
+    c = std::max<long long>(c, a.lds_acc ? 1024 : 256);
+    a.chunk = (int)std::min<long long>(c, 16384);
+    a.err = (ctx->flags & NURBS_VALIDATE) ? reinterpret_cast<int*>(ws) : nullptr;
+    return a;
+}
+
+}  // namespace
+
+int nurbs_surface_uv_ws_bytes(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, int npts, unsigned grad_mask,
+                              size_t* out) {
+    int rc = uv_common(ctx, B, p, q, nu_c, nv_c, npts);
+    if (rc) return rc;
+    if (!out) return fail(ctx, NURBS_EINVAL, "out is NULL");
+    if (grad_mask & ~NURBS_GRAD_ALL) return fail(ctx, NURBS_EINVAL, "unknown gradient bits");
+    if (grad_mask == 0) *out = (ctx->flags & NURBS_VALIDATE) ? kWsHeader : 0;
+    else *out = uv_layout(B, p, q, nu_c, nv_c).total;
+    return NURBS_OK;
+}
+
+int nurbs_surface_uv_fwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, const float* ctrl, const float* w,
+                         const float* ku, const float* kv, int npts, const float* uv, int uv_shared, float* pts,
+                         float* pts_du, float* pts_dv, void* ws, size_t ws_bytes, void* stream) {
+    int rc = uv_common(ctx, B, p, q, nu_c, nv_c, npts);
+    if (rc) return rc;
+    if (!pts && !pts_du && !pts_dv) return fail(ctx, NURBS_EINVAL, "no output requested");
+    if (B == 0 || npts == 0) return NURBS_OK;
+    if (!ctrl || !w || !ku || !kv || !uv) return fail(ctx, NURBS_EINVAL, "NULL array");
+    if ((ctx->flags & NURBS_VALIDATE) && (!ws || ws_bytes < kWsHeader))
+        return fail(ctx, NURBS_EWORKSPACE, "NURBS_VALIDATE needs a workspace");
+    const UvArgs a = uv_args(ctx, B, p, q, nu_c, nv_c, npts, ctrl, w, ku, kv, uv, uv_shared, ws);
+    hipError_t e = launch_uv_fwd(a, reinterpret_cast<hipStream_t>(stream), pts, pts_du, pts_dv);
+    return e ? hip_fail(ctx, e, "launch uv forward") : NURBS_OK;
+}
+
+int nurbs_surface_uv_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, const float* ctrl, const float* w,
+                         const float* ku, const float* kv, int npts, const float* uv, int uv_shared,
+                         const float* grad_pts, float* grad_ctrl, float* grad_w, float* grad_ku, float* grad_kv,
+                         unsigned grad_mask, void* ws, size_t ws_bytes, void* stream) {
+    int rc = uv_common(ctx, B, p, q, nu_c, nv_c, npts);
+    if (rc) return rc;
+    if (grad_mask & ~NURBS_GRAD_ALL) return fail(ctx, NURBS_EINVAL, "unknown gradient bits");
+    if (grad_mask == 0 || B == 0) return NURBS_OK;
+    if (((grad_mask & NURBS_GRAD_CTRL) && !grad_ctrl) || ((grad_mask & NURBS_GRAD_W) && !grad_w) ||
+        ((grad_mask & NURBS_GRAD_KU) && !grad_ku) || ((grad_mask & NURBS_GRAD_KV) && !grad_kv))
+        return fail(ctx, NURBS_EINVAL, "NULL gradient output for a requested gradient");
+    if (!ctrl || !w || !ku || !kv) return fail(ctx, NURBS_EINVAL, "NULL array");
+    const UvLayout l = uv_layout(B, p, q, nu_c, nv_c);
+    if (!ws || ws_bytes < l.total) return fail(ctx, NURBS_EWORKSPACE, "workspace too small: need " + std::to_string(l.total));
+    if (npts > 0 && (!uv || !grad_pts)) return fail(ctx, NURBS_EINVAL, "NULL uv or grad_pts");
+    const UvArgs a = uv_args(ctx, B, p, q, nu_c, nv_c, npts, ctrl, w, ku, kv, uv, uv_shared, ws);
+    char* wb = reinterpret_cast<char*>(ws);
+    hipError_t e = launch_uv_bwd(a, reinterpret_cast<hipStream_t>(stream), grad_pts, grad_mask,
+                                 reinterpret_cast<unsigned*>(wb + l.maxbits),
+                                 reinterpret_cast<unsigned long long*>(wb + l.acc), grad_ctrl, grad_w, grad_ku, grad_kv);
+    return e ? hip_fail(ctx, e, "launch uv backward") : NURBS_OK;
+}
+
+// --------------------------------------------------------------------------
 // point-set losses
 // --------------------------------------------------------------------------
 namespace {

@@ -105,6 +105,20 @@ hipError_t launch_curve_fwd(int p, int dim, hipStream_t st, const CurveArgs& a, 
 hipError_t launch_curve_bwd(int p, int dim, hipStream_t st, const CurveArgs& a, const float* gpts, float* gctrl,
                             float* gw, float* gk, float* part, unsigned mask);
 
+// surfaces at scattered (u, v) pairs: B surfaces of one shape (k_uv.hip)
+struct UvArgs {
+    const float *ctrl, *w, *ku, *kv, *uv;  // uv [B or 1][npts][2]
+    int B, p, q, nu_c, nv_c, npts, uv_shared;
+    int chunk;    // pairs per backward workgroup
+    int nacc;     // 64-bit accumulators per surface: 4 nu_c nv_c + nU + nV
+    int lds_acc;  // accumulate in LDS first (nacc * 8 bytes fit)
+    int* err;     // device error word (NURBS_VALIDATE) or NULL
+};
+constexpr int kUvLdsAccMax = 7424;  // accumulators a workgroup keeps in LDS (58 KiB)
+hipError_t launch_uv_fwd(const UvArgs& a, hipStream_t st, float* pts, float* du, float* dv);
+hipError_t launch_uv_bwd(const UvArgs& a, hipStream_t st, const float* gpts, unsigned mask, unsigned* maxbits,
+                         unsigned long long* acc, float* gc, float* gw, float* gku, float* gkv);
+
 // point-set losses (k_chamfer.hip)
 struct NnSplit {
     int nranges;  // target ranges (workgroups along the target set)

@@ -349,6 +349,54 @@ def curve_batch(seed: int = 5, B: int = 64, p: int = 3, nc: int = 16, ns: int = 
 
 
 # --------------------------------------------------------------------------
+# surfaces at scattered (u, v) pairs
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class UvBatch:
+    """B surfaces of one shape and their scattered parameter pairs:
+    ``ctrl [B][nu_c][nv_c][3]``, ``w [B][nu_c][nv_c]``, ``ku [B][nu_c+p+1]``,
+    ``kv [B][nv_c+q+1]``, ``uv [npts][2]`` (shared) or ``[B][npts][2]``,
+    ``upstream [B][npts][3]`` (dL/dS)."""
+
+    name: str
+    p: int
+    q: int
+    ctrl: np.ndarray
+    w: np.ndarray
+    ku: np.ndarray
+    kv: np.ndarray
+    uv: np.ndarray
+    upstream: np.ndarray
+
+    @property
+    def B(self) -> int:
+        return int(self.ctrl.shape[0])
+
+    @property
+    def npts(self) -> int:
+        return int(self.uv.shape[-2])
+
+
+def uv_batch(seed: int = 7, B: int = 4, p: int = 3, q: int = 3, nu_c: int = 16, nv_c: int = 16,
+             npts: int = 4096, repeat: float = 0.1, shared_uv: bool = False) -> UvBatch:
+    """Perturbed-lattice nets (as the grids), weights U(0.5, 1.5), clamped
+    random knots with ``repeat`` repeated interior knots, and npts pairs
+    drawn U(0,1)^2 in random order -- the parameters a point cloud carries
+    (the paper's point-cloud fits).  dL/dS ~ U(-0.1, 0.1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ctrl = np.stack([perturbed_lattice(rng, nu_c, nv_c) for _ in range(B)])
+    w = rng.uniform(0.5, 1.5, (B, nu_c, nv_c)).astype(np.float32)
+    ku = np.stack([clamped_random_knots(rng, nu_c, p, repeat) for _ in range(B)])
+    kv = np.stack([clamped_random_knots(rng, nv_c, q, repeat) for _ in range(B)])
+    shape = (npts, 2) if shared_uv else (B, npts, 2)
+    uv = rng.uniform(0.0, 1.0, shape).astype(np.float32)
+    up = rng.uniform(-0.1, 0.1, (B, npts, 3)).astype(np.float32)
+    return UvBatch(name=f"uv_{B}x{nu_c}x{nv_c}_p{p}q{q}_{npts}", p=p, q=q, ctrl=ctrl, w=w, ku=ku, kv=kv, uv=uv,
+                   upstream=up)
+
+
+# --------------------------------------------------------------------------
 # point sets for the Chamfer / Hausdorff losses
 # --------------------------------------------------------------------------
 
