@@ -481,8 +481,10 @@ def chamfer_leg(steps: int):
 
 def fit_leg(steps: int):
     """The fitting loop (64x64 bicubic net, 512x512 samples of
-    z = sin 3x cos 3y, Adam lr 1e-2 on points, weights and knots), one HIP
-    graph launch per step."""
+    z = sin 3x cos 3y, Adam lr 1e-2), one HIP graph launch per step, in three
+    variants: points, weights and knots trained; knots fixed with the span and
+    basis tables built once (the fixed-knot layer); knots fixed, basis
+    evaluated every step."""
     import torch
     from paper_2104_14547_amd import workloads as W
     from paper_2104_14547_amd.fit import SurfaceFit
@@ -490,17 +492,22 @@ def fit_leg(steps: int):
     d = b.surface(0)
     dev = torch.device("cuda", 0)
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    f = SurfaceFit(T(d["ctrl"]), T(d["w"]), T(d["ku"]), T(d["kv"]), d["p"], d["q"], T(d["us"]), T(d["vs"]),
-                   T(d["target"]), lr=1e-2, train_knots=True, graph=True)
-    l0 = f.loss()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    f.step(steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return {"workload": b.name, "steps": steps, "step_ms": dt / steps * 1e3,
-            "pts_per_s": b.n_points * steps / dt, "loss_start": l0, "loss_end": f.loss(),
-            "note": "whole step (fwd, dL/dS, bwd, Adam, projections) replayed as one HIP graph"}
+    out = {"workload": b.name, "steps": steps,
+           "note": "whole step (fwd, dL/dS, bwd, Adam, projections) replayed as one HIP graph"}
+    for name, kw in (("knots_trained", dict(train_knots=True)),
+                     ("fixed_knots_tables", dict(train_knots=False, cached_basis=True)),
+                     ("fixed_knots_no_tables", dict(train_knots=False, cached_basis=False))):
+        f = SurfaceFit(T(d["ctrl"]), T(d["w"]), T(d["ku"]), T(d["kv"]), d["p"], d["q"], T(d["us"]), T(d["vs"]),
+                       T(d["target"]), lr=1e-2, graph=True, **kw)
+        l0 = f.loss()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"step_ms": dt / steps * 1e3, "pts_per_s": b.n_points * steps / dt, "loss_start": l0,
+                     "loss_end": f.loss(), "tiles": list(f.tiling)}
+    return out
 
 
 def copy_calibration(torch, dev, mib: int, reps: int = 3):

@@ -180,6 +180,48 @@ int nurbs_surface_bwd(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
                       float *grad_kv, unsigned grad_mask, void *ws,
                       size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Fixed knots: the B-spline layer with a precomputed basis (Appendix E's
+ * layer whose basis is computed once; the fixed-knot fits of Sec. 4.2).
+ * While the knots and samples do not change, the span and the p+1 basis
+ * values of every sample are computed once into a table and the grid calls
+ * below read them instead of searching and evaluating the recursion.
+ * Knot gradients are not available on these calls (the knots are fixed).
+ *
+ * Table layout (device memory, caller-owned): int32 spans [nx], then, at
+ * the next multiple of 256 bytes, float basis [nx][p+1]; the same values
+ * nurbs_find_spans and nurbs_basis return.
+ * ---------------------------------------------------------------------- */
+int nurbs_basis_table_bytes(int p, int nx, size_t *out);
+/* Fills `table` for parameters x [nx] on the knot vector knots [n_knots]
+ * (n_knots <= NURBS_MAX_KNOTS).  NURBS_EWORKSPACE if table_bytes is below
+ * nurbs_basis_table_bytes(p, nx). */
+int nurbs_basis_table_build(const float *knots, int n_knots, int p, const float *x, int nx,
+                            void *table, size_t table_bytes, void *stream);
+
+/* nurbs_surface_fwd / nurbs_surface_bwd with the tables of the u samples
+ * (degree p, nu_s samples) and the v samples (degree q, nv_s samples):
+ * tab_shared != 0: one pair of tables for the whole batch (every surface
+ * has the same knots and samples); else B tables each, back to back with a
+ * stride of nurbs_basis_table_bytes.  The tables must have been built from
+ * the ku, kv, us, vs passed here (which the kernels still stage).  The
+ * backward's grad_mask takes NURBS_GRAD_CTRL and NURBS_GRAD_W only;
+ * workspace as nurbs_surface_ws_bytes with that mask.  Results equal those
+ * of the calls without tables bit for bit. */
+int nurbs_surface_fwd_tab(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
+                          const float *ctrl, const float *w, const float *ku,
+                          const float *kv, int nu_s, int nv_s, const float *us,
+                          const float *vs, int uv_shared, const void *tab_u,
+                          const void *tab_v, int tab_shared, float *pts, void *ws,
+                          size_t ws_bytes, void *stream);
+int nurbs_surface_bwd_tab(nurbs_ctx *ctx, int B, int p, int q, int nu_c, int nv_c,
+                          const float *ctrl, const float *w, const float *ku,
+                          const float *kv, int nu_s, int nv_s, const float *us,
+                          const float *vs, int uv_shared, const void *tab_u,
+                          const void *tab_v, int tab_shared, const float *grad_pts,
+                          float *grad_ctrl, float *grad_w, unsigned grad_mask, void *ws,
+                          size_t ws_bytes, void *stream);
+
 /* The same backward for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): no workspace argument; the tile slots live in a 64 MiB array

@@ -45,6 +45,7 @@ EXPORTS = (
     "nurbs_surface_bwd_noalloc",
     "nurbs_chamfer_ws_bytes", "nurbs_nearest", "nurbs_chamfer",
     "nurbs_surface_uv_ws_bytes", "nurbs_surface_uv_fwd", "nurbs_surface_uv_bwd",
+    "nurbs_basis_table_bytes", "nurbs_basis_table_build", "nurbs_surface_fwd_tab", "nurbs_surface_bwd_tab",
 )
 
 
@@ -93,6 +94,12 @@ _SIGS = {
     "nurbs_read_device_error": (_i, [_vp, _vp, _ip]),
     "nurbs_surface_bwd_noalloc": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _i, _vp,
                                        _vp, _vp, _vp, _vp, _u, _vp]),
+    "nurbs_basis_table_bytes": (_i, [_i, _i, _szp]),
+    "nurbs_basis_table_build": (_i, [_vp, _i, _i, _vp, _i, _vp, _sz, _vp]),
+    "nurbs_surface_fwd_tab": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _i, _vp, _vp, _i,
+                                   _vp, _vp, _sz, _vp]),
+    "nurbs_surface_bwd_tab": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _i, _vp, _vp, _i,
+                                   _vp, _vp, _vp, _u, _vp, _sz, _vp]),
     "nurbs_surface_uv_ws_bytes": (_i, [_vp, _i, _i, _i, _i, _i, _i, _u, _szp]),
     "nurbs_surface_uv_fwd": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz,
                                   _vp]),

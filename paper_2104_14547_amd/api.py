@@ -209,6 +209,91 @@ def surface_bwd(ctrl, w, ku, kv, p: int, q: int, us, vs, grad_pts, mask: int = N
     return res
 
 
+# --------------------------------------------------------------------------
+# fixed knots: precomputed span and basis tables
+# --------------------------------------------------------------------------
+
+def basis_table_bytes(p: int, nx: int) -> int:
+    out = ctypes.c_size_t()
+    _check(N.lib().nurbs_basis_table_bytes(int(p), int(nx), ctypes.byref(out)))
+    return out.value
+
+
+def basis_table(knots, p: int, x):
+    """Span and basis table(s) of the parameters x on the knots
+    (nurbs_basis_table_build): knots [n_knots], x [nx] give one table;
+    knots [B, n_knots], x [B, nx] (or [nx]) give B tables back to back.
+    Returns a uint8 device tensor [B, table_bytes] (B = 1 for one table)."""
+    _need_cuda_f32("knots", knots)
+    _need_cuda_f32("x", x)
+    kn = knots if knots.dim() == 2 else knots[None]
+    B, nx = int(kn.shape[0]), int(x.shape[-1])
+    xs = x if x.dim() == 2 else x[None].expand(B, nx)
+    nb = basis_table_bytes(p, nx)
+    out = torch.empty((B, nb), dtype=torch.uint8, device=knots.device)
+    st = _stream(knots.device)
+    for b in range(B):
+        xb = xs[b].contiguous()
+        _check(N.lib().nurbs_basis_table_build(_ptr(kn[b]), int(kn.shape[1]), int(p), _ptr(xb), nx,
+                                               out[b].data_ptr(), nb, st))
+    return out
+
+
+def _tab_shared(tab_u, tab_v, B):
+    if tab_u.dim() != 2 or tab_v.dim() != 2 or tab_u.shape[0] != tab_v.shape[0] or tab_u.shape[0] not in (1, B):
+        raise ValueError("tables must be [1, bytes] (shared) or [B, bytes]")
+    return 1 if tab_u.shape[0] == 1 else 0
+
+
+def surface_fwd_tab(ctrl, w, ku, kv, p: int, q: int, us, vs, tab_u, tab_v, out=None, ctx: Context | None = None):
+    """Points of a uniform batch on fixed knots from precomputed basis tables
+    (nurbs_surface_fwd_tab); tab_u, tab_v from ``basis_table``."""
+    squeeze = ctrl.dim() == 3
+    ctrl, w, ku, kv, B, nu_c, nv_c, nu_s, nv_s, shared = _uniform_shapes(ctrl, w, ku, kv, p, q, us, vs)
+    ctx = ctx or context(ctrl.device.index)
+    if out is None:
+        out = torch.empty((B, nu_s, nv_s, 3), dtype=torch.float32, device=ctrl.device)
+    ts = _tab_shared(tab_u, tab_v, B)
+    ws = torch.zeros(256, dtype=torch.uint8, device=ctrl.device) if ctx.validate else None
+    ctx.last_ws = ws
+    _check(N.lib().nurbs_surface_fwd_tab(ctx.handle, B, p, q, nu_c, nv_c, _ptr(ctrl), _ptr(w), _ptr(ku), _ptr(kv),
+                                         nu_s, nv_s, _ptr(us), _ptr(vs), shared, _ptr(tab_u), _ptr(tab_v), ts,
+                                         _ptr(out), _ptr(ws), 0 if ws is None else 256, _stream(ctrl.device)),
+           ctx.handle)
+    return out[0] if squeeze else out
+
+
+def surface_bwd_tab(ctrl, w, ku, kv, p: int, q: int, us, vs, tab_u, tab_v, grad_pts,
+                    mask: int = N.NURBS_GRAD_CTRL | N.NURBS_GRAD_W, ctx: Context | None = None):
+    """(dL/dctrl, dL/dw) on fixed knots from precomputed basis tables
+    (nurbs_surface_bwd_tab)."""
+    squeeze = ctrl.dim() == 3
+    ctrl, w, ku, kv, B, nu_c, nv_c, nu_s, nv_s, shared = _uniform_shapes(ctrl, w, ku, kv, p, q, us, vs)
+    grad_pts = grad_pts.contiguous()
+    if squeeze:
+        grad_pts = grad_pts[None]
+    _need_cuda_f32("grad_pts", grad_pts)
+    ctx = ctx or context(ctrl.device.index)
+    dev = ctrl.device
+    gc = torch.empty_like(ctrl) if mask & N.NURBS_GRAD_CTRL else None
+    gw = torch.empty_like(w) if mask & N.NURBS_GRAD_W else None
+    ts = _tab_shared(tab_u, tab_v, B)
+    ws_n = ctypes.c_size_t()
+    _check(N.lib().nurbs_surface_ws_bytes(ctx.handle, B, p, q, nu_c, nv_c, nu_s, nv_s, mask,
+                                          ctypes.byref(ws_n)), ctx.handle)
+    ws = torch.empty(ws_n.value, dtype=torch.uint8, device=dev) if ws_n.value else None
+    if ws is not None and ctx.validate:
+        ws[:256].zero_()
+    ctx.last_ws = ws
+    _check(N.lib().nurbs_surface_bwd_tab(ctx.handle, B, p, q, nu_c, nv_c, _ptr(ctrl), _ptr(w), _ptr(ku), _ptr(kv),
+                                         nu_s, nv_s, _ptr(us), _ptr(vs), shared, _ptr(tab_u), _ptr(tab_v), ts,
+                                         _ptr(grad_pts), _ptr(gc), _ptr(gw), int(mask), _ptr(ws), ws_n.value,
+                                         _stream(dev)), ctx.handle)
+    if squeeze:
+        return (None if gc is None else gc[0]), (None if gw is None else gw[0])
+    return gc, gw
+
+
 class NurbsSurfaceFn(torch.autograd.Function):
     """Differentiable uniform-batch evaluation; the backward is the library's
     hand-written adjoint (no autograd tape through the kernels)."""

@@ -229,6 +229,8 @@ UniformArgs make_uargs(const nurbs_ctx* ctx, const UniformGeom& g, bool bwd, int
     a.ntiles = (int)(bwd ? g.tiles_b : g.tiles_f);
     a.flags = ctx->flags;
     a.err = (ctx->flags & NURBS_VALIDATE) ? reinterpret_cast<int*>(ws) : nullptr;
+    a.tab_u = a.tab_v = nullptr;
+    a.tab_u_stride = a.tab_v_stride = 0;
     return a;
 }
 
@@ -348,6 +350,117 @@ int nurbs_surface_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, c
 #undef ND_CASE
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "launch backward");
+    return NURBS_OK;
+}
+
+// --------------------------------------------------------------------------
+// fixed knots: precomputed span and basis tables
+// --------------------------------------------------------------------------
+namespace {
+size_t table_bytes(int d, int n) { return basis_table_split(n) + sizeof(float) * (size_t)n * (d + 1); }
+}  // namespace
+
+int nurbs_basis_table_bytes(int p, int nx, size_t* out) {
+    if (p < 1 || p > NURBS_MAX_DEGREE) return fail(nullptr, NURBS_EDEGREE, "degree");
+    if (nx < 0 || !out) return fail(nullptr, NURBS_EINVAL, "bad arguments");
+    *out = table_bytes(p, nx);
+    return NURBS_OK;
+}
+
+int nurbs_basis_table_build(const float* knots, int n_knots, int p, const float* x, int nx, void* table,
+                            size_t table_bytes_avail, void* stream) {
+    if (p < 1 || p > NURBS_MAX_DEGREE) return fail(nullptr, NURBS_EDEGREE, "degree");
+    if (n_knots < 2 * p + 2 || n_knots > NURBS_MAX_KNOTS || nx < 0 || !knots || (nx > 0 && (!x || !table)))
+        return fail(nullptr, NURBS_EINVAL, "bad arguments");
+    if (nx == 0) return NURBS_OK;
+    if (table_bytes_avail < table_bytes(p, nx)) return fail(nullptr, NURBS_EWORKSPACE, "table too small");
+    char* t = reinterpret_cast<char*>(table);
+    hipError_t e = launch_spans(p, reinterpret_cast<hipStream_t>(stream), knots, n_knots, x, nx,
+                                reinterpret_cast<int32_t*>(t), reinterpret_cast<float*>(t + basis_table_split(nx)));
+    return e ? hip_fail(nullptr, e, "launch k_spans") : NURBS_OK;
+}
+
+namespace {
+void bind_tables(UniformArgs& a, int p, int q, const void* tab_u, const void* tab_v, int tab_shared) {
+    a.tab_u = reinterpret_cast<const char*>(tab_u);
+    a.tab_v = reinterpret_cast<const char*>(tab_v);
+    a.tab_u_stride = tab_shared ? 0 : table_bytes(p, a.nu_s);
+    a.tab_v_stride = tab_shared ? 0 : table_bytes(q, a.nv_s);
+}
+}  // namespace
+
+int nurbs_surface_fwd_tab(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, const float* ctrl,
+                          const float* w, const float* ku, const float* kv, int nu_s, int nv_s, const float* us,
+                          const float* vs, int uv_shared, const void* tab_u, const void* tab_v, int tab_shared,
+                          float* pts, void* ws, size_t ws_bytes, void* stream) {
+    int rc = uniform_common(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
+    if (rc) return rc;
+    if (B == 0 || nu_s == 0 || nv_s == 0) return NURBS_OK;
+    if (!ctrl || !w || !ku || !kv || !us || !vs || !pts || !tab_u || !tab_v)
+        return fail(ctx, NURBS_EINVAL, "NULL array");
+    if ((ctx->flags & NURBS_VALIDATE) && (!ws || ws_bytes < kWsHeader))
+        return fail(ctx, NURBS_EWORKSPACE, "NURBS_VALIDATE needs a workspace");
+    const UniformGeom g = uniform_geom(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
+    if (g.tiles_f > (1ll << 30)) return fail(ctx, NURBS_EINVAL, "batch too large");
+    UniformArgs a = make_uargs(ctx, g, false, B, nu_c, nv_c, nu_s, nv_s, ctrl, w, ku, kv, us, vs, uv_shared, ws);
+    bind_tables(a, p, q, tab_u, tab_v, tab_shared);
+    const dim3 grid((unsigned)((g.tiles_f + kWavesPerWG - 1) / kWavesPerWG));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipErrorInvalidValue;
+    switch (p) {
+#define ND_CASE(P) case P: e = launch_uniform_fwd_p##P(q, grid, st, a, pts); break;
+        ND_CASE(1) ND_CASE(2) ND_CASE(3) ND_CASE(4) ND_CASE(5) ND_CASE(6) ND_CASE(7)
+#undef ND_CASE
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "launch forward (tables)");
+    return NURBS_OK;
+}
+
+int nurbs_surface_bwd_tab(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, const float* ctrl,
+                          const float* w, const float* ku, const float* kv, int nu_s, int nv_s, const float* us,
+                          const float* vs, int uv_shared, const void* tab_u, const void* tab_v, int tab_shared,
+                          const float* grad_pts, float* grad_ctrl, float* grad_w, unsigned grad_mask, void* ws,
+                          size_t ws_bytes, void* stream) {
+    int rc = uniform_common(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
+    if (rc) return rc;
+    if (grad_mask & ~(NURBS_GRAD_CTRL | NURBS_GRAD_W))
+        return fail(ctx, NURBS_EINVAL, "fixed knots: gradient bits are NURBS_GRAD_CTRL and NURBS_GRAD_W only");
+    if (grad_mask == 0 || B == 0) return NURBS_OK;
+    if (((grad_mask & NURBS_GRAD_CTRL) && !grad_ctrl) || ((grad_mask & NURBS_GRAD_W) && !grad_w))
+        return fail(ctx, NURBS_EINVAL, "NULL gradient output for a requested gradient");
+    if (!ctrl || !w || !ku || !kv || !us || !vs) return fail(ctx, NURBS_EINVAL, "NULL array");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (nu_s == 0 || nv_s == 0) {
+        const size_t cp = (size_t)B * nu_c * nv_c;
+        hipError_t e = hipSuccess;
+        if (grad_mask & NURBS_GRAD_CTRL) e = launch_zero(st, grad_ctrl, cp * 3);
+        if (!e && (grad_mask & NURBS_GRAD_W)) e = launch_zero(st, grad_w, cp);
+        return e ? hip_fail(ctx, e, "zero fill") : NURBS_OK;
+    }
+    if (!grad_pts || !tab_u || !tab_v) return fail(ctx, NURBS_EINVAL, "NULL grad_pts or table");
+    const UniformGeom g = uniform_geom(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
+    const size_t need = kWsHeader + (size_t)g.tiles_b * g.slot;
+    if (!ws || ws_bytes < need) return fail(ctx, NURBS_EWORKSPACE, "workspace too small: need " + std::to_string(need));
+    if (g.tiles_b > (1ll << 30)) return fail(ctx, NURBS_EINVAL, "batch too large");
+    const long long fin_items = (long long)B * fin_parts(nu_c, nv_c);
+    if (fin_items > (1ll << 30)) return fail(ctx, NURBS_EINVAL, "batch too large");
+    UniformArgs a = make_uargs(ctx, g, true, B, nu_c, nv_c, nu_s, nv_s, ctrl, w, ku, kv, us, vs, uv_shared, ws);
+    bind_tables(a, p, q, tab_u, tab_v, tab_shared);
+    char* slots = reinterpret_cast<char*>(ws) + kWsHeader;
+    const dim3 grid((unsigned)((g.tiles_b + kWavesPerWG - 1) / kWavesPerWG));
+    hipError_t e = hipErrorInvalidValue;
+    switch (p) {
+#define ND_CASE(P)                                                                                        \
+    case P:                                                                                               \
+        e = launch_uniform_bwd_p##P(q, grid, st, a, grad_pts, slots, g.slot, grad_mask);                  \
+        if (e == hipSuccess)                                                                              \
+            e = launch_uniform_fin_p##P(q, dim3((fin_items + kWavesPerWG - 1) / kWavesPerWG), st, a, slots,  \
+                                        g.slot, grad_ctrl, grad_w, nullptr, nullptr, grad_mask);          \
+        break;
+        ND_CASE(1) ND_CASE(2) ND_CASE(3) ND_CASE(4) ND_CASE(5) ND_CASE(6) ND_CASE(7)
+#undef ND_CASE
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "launch backward (tables)");
     return NURBS_OK;
 }
 

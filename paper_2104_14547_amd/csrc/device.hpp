@@ -256,6 +256,12 @@ struct Surf {
     const float* __restrict__ us;    // [nu_s]
     const float* __restrict__ vs;    // [nv_s]
     int nu_c, nv_c, nu_s, nv_s;
+    // Fixed-knot tables (read only by kernels built for them): the span of
+    // every sample and its basis row, [nu_s] and [nu_s][p+1] (v likewise).
+    const int* __restrict__ tsu;
+    const float* __restrict__ tbu;
+    const int* __restrict__ tsv;
+    const float* __restrict__ tbv;
 };
 
 // homogeneous control point Pw_ij = (w x, w y, w z, w)

@@ -239,15 +239,50 @@ __device__ __forceinline__ TileIn stage_tile(const Surf& sg, int p, int q, int c
     return in;
 }
 
+// Fixed-knot tables: the column's span and basis, and those of the lane's
+// row in the tile's first 64-row chunk, loaded before stage_tile so that
+// its final wait covers them (one memory latency for all first inputs).
+template <int QM>
+struct ColPre {
+    int k;
+    float N[QM + 1];
+};
+template <int P>
+struct RowPre {
+    int k;
+    float N[P + 1];
+};
+template <int QM>
+__device__ __forceinline__ void col_prefetch(const Surf& s, int q, int col0, ColPre<QM>& c) {
+    const int bc = min(col0 + lane_id(), s.nv_s - 1);
+    c.k = s.tsv[bc];
+#pragma unroll
+    for (int h = 0; h <= QM; ++h) c.N[h] = h <= q ? s.tbv[(size_t)bc * (q + 1) + h] : 0.f;
+}
+template <int P>
+__device__ __forceinline__ void row_prefetch(const Surf& s, int row0, int row1, RowPre<P>& r) {
+    const int ra = row0 + min(lane_id(), min(kWave, row1 - row0) - 1);
+    r.k = s.tsu[ra];
+#pragma unroll
+    for (int i = 0; i <= P; ++i) r.N[i] = s.tbu[(size_t)ra * (P + 1) + i];
+}
+
 // Column set-up shared by forward and backward: this lane's v-span and
 // basis, and the tile's control-column range [j0, j0 + ncols).
-template <int QM>
+template <int QM, bool TAB = false>
 __device__ __forceinline__ int tile_columns(const Surf& s, int q, int col0, float vb, float Nv[QM + 1], bool& act,
-                                            int& j0, int& ncols) {
+                                            int& j0, int& ncols, const ColPre<QM>* pre = nullptr) {
     const int lane = lane_id();
     const int b = col0 + lane;
     act = b < s.nv_s;
-    const int kb = sample_basis_rt<QM>(s.kv, s.nv_c, vb, q, Nv);
+    int kb;
+    if constexpr (TAB) {  // fixed knots: the column's span and basis, prefetched from the table
+        kb = pre->k;
+#pragma unroll
+        for (int h = 0; h <= QM; ++h) Nv[h] = pre->N[h];
+    } else {
+        kb = sample_basis_rt<QM>(s.kv, s.nv_c, vb, q, Nv);
+    }
     const int nact = min(kWave, s.nv_s - col0);
     const int kfirst = bcast_lane(kb, 0);
     const int klast = bcast_lane(kb, nact - 1);
@@ -264,17 +299,38 @@ struct FwdLds {
     float knots[2][kWG];
 };
 
-template <int P, int QM, bool BLK>
+// The span and basis of row a0 + min(lane, nr - 1): from the fixed-knot
+// table, or evaluated from the parameter ua.
+template <int P, bool TAB>
+__device__ __forceinline__ int row_basis(const Surf& s, int a0, int nr, float ua, float Nu_l[P + 1],
+                                         const RowPre<P>* pre) {
+    if constexpr (TAB) {
+        if (pre) {  // the tile's first chunk: prefetched with the tile's first inputs
+#pragma unroll
+            for (int r = 0; r <= P; ++r) Nu_l[r] = pre->N[r];
+            return pre->k;
+        }
+        const int ra = a0 + min(lane_id(), nr - 1);
+#pragma unroll
+        for (int r = 0; r <= P; ++r) Nu_l[r] = s.tbu[(size_t)ra * (P + 1) + r];
+        return s.tsu[ra];
+    } else {
+        return sample_basis<P>(s.ku, s.nu_c, ua, Nu_l);
+    }
+}
+
+template <int P, int QM, bool BLK, bool TAB = false>
 __device__ __forceinline__ void fwd_rows(const Surf& s, Block& bk, const float Nv[QM + 1], int q, int jb, bool act,
-                                         int row0, int row1, float u0, float* __restrict__ orow, size_t ostride) {
+                                         int row0, int row1, float u0, float* __restrict__ orow, size_t ostride,
+                                         const RowPre<P>* rpre = nullptr) {
     const int lane = lane_id();
     float4 R[P + 1];
     int cur = -1;  // window rows cur-P .. cur
     for (int a0 = row0; a0 < row1; a0 += kWave) {
         const int nr = min(kWave, row1 - a0);
         float Nu_l[P + 1];
-        const float ua = a0 == row0 ? u0 : s.us[a0 + min(lane, nr - 1)];
-        const int ka_l = sample_basis<P>(s.ku, s.nu_c, ua, Nu_l);
+        const float ua = TAB ? 0.f : (a0 == row0 ? u0 : s.us[a0 + min(lane, nr - 1)]);
+        const int ka_l = row_basis<P, TAB>(s, a0, nr, ua, Nu_l, a0 == row0 ? rpre : nullptr);
         for (int t = 0; t < nr; ++t) {
             const int ka = bcast_lane(ka_l, t);
             if (ka != cur) {
@@ -319,28 +375,34 @@ __device__ __forceinline__ void fwd_rows(const Surf& s, Block& bk, const float N
     }
 }
 
-template <int P, int QM>
+template <int P, int QM, bool TAB = false>
 __device__ __forceinline__ void fwd_tile(const Surf& sg, int q, int col0, int row0, int row1,
                                          float* __restrict__ pts, FwdLds* lds) {
     const int lane = lane_id();
     const int b = col0 + lane;
     // knots from LDS from here on
     Surf s = sg;
+    ColPre<QM> cpre;
+    RowPre<P> rpre;
+    if constexpr (TAB) {
+        col_prefetch<QM>(sg, q, col0, cpre);
+        row_prefetch<P>(sg, row0, row1, rpre);
+    }
     const TileIn in = stage_tile(sg, P, q, col0, row0, row1, lds->knots[0], lds->knots[1]);
     s.ku = lds->knots[0];
     s.kv = lds->knots[1];
     float Nv[QM + 1];
     bool act;
     int j0, ncols;
-    const int kb = tile_columns<QM>(s, q, col0, in.v, Nv, act, j0, ncols);
+    const int kb = tile_columns<QM, TAB>(s, q, col0, in.v, Nv, act, j0, ncols, &cpre);
     const int jb = kb - q;
     Block bk = make_block(lds->blk, j0, ncols, P);
     float* orow = pts + 3 * ((size_t)row0 * s.nv_s + b);
     const size_t ostride = 3 * (size_t)s.nv_s;
     if (bk.on)
-        fwd_rows<P, QM, true>(s, bk, Nv, q, jb, act, row0, row1, in.u0, orow, ostride);
+        fwd_rows<P, QM, true, TAB>(s, bk, Nv, q, jb, act, row0, row1, in.u0, orow, ostride, &rpre);
     else
-        fwd_rows<P, QM, false>(s, bk, Nv, q, jb, act, row0, row1, in.u0, orow, ostride);
+        fwd_rows<P, QM, false, TAB>(s, bk, Nv, q, jb, act, row0, row1, in.u0, orow, ostride, &rpre);
 }
 
 // --------------------------------------------------------------------------
@@ -704,12 +766,13 @@ __device__ __forceinline__ void flush_row(const Surf& s, BwdState<QM>& st, const
 
 // Column set-up of a backward tile (independent of the degree in u): the
 // lane's v-span and basis, and the segment structure of the spans.
-template <int QM>
-__device__ __forceinline__ void bwd_columns(const Surf& s, int q, int col0, float vb, BwdState<QM>& st, BwdLds* L) {
+template <int QM, bool TAB = false>
+__device__ __forceinline__ void bwd_columns(const Surf& s, int q, int col0, float vb, BwdState<QM>& st, BwdLds* L,
+                                            const ColPre<QM>* pre = nullptr) {
     const int lane = lane_id();
     st.q = q;
     int j0, ncols;
-    st.kb = tile_columns<QM>(s, q, col0, vb, st.Nv, st.act, j0, ncols);
+    st.kb = tile_columns<QM, TAB>(s, q, col0, vb, st.Nv, st.act, j0, ncols, pre);
     st.jb = st.kb - q;
 #pragma unroll
     for (int h = 0; h <= QM; ++h) st.f[h] = 0.f;
@@ -766,10 +829,10 @@ __device__ __forceinline__ float3 load_g(const float* __restrict__ gpts, int a, 
     return v;
 }
 
-template <int P, int QM, bool BLK>
+template <int P, int QM, bool BLK, bool TAB = false>
 __device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, Block& bk, int col0, int row0,
                                               int row1, float u0, const float* __restrict__ gpts, SlotView out,
-                                              BwdLds* L, unsigned mask) {
+                                              BwdLds* L, unsigned mask, const RowPre<P>* rpre = nullptr) {
     const int lane = lane_id();
     const bool want_pw = (mask & 3u) != 0;
     const bool want_ku = (mask & 4u) != 0;
@@ -783,8 +846,8 @@ __device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, B
     for (int a0 = row0; a0 < row1; a0 += kWave) {
         const int nr = min(kWave, row1 - a0);
         float Nu_l[P + 1];
-        const float ua = a0 == row0 ? u0 : s.us[a0 + min(lane, nr - 1)];
-        const int ka_l = sample_basis<P>(s.ku, s.nu_c, ua, Nu_l);
+        const float ua = TAB ? 0.f : (a0 == row0 ? u0 : s.us[a0 + min(lane, nr - 1)]);
+        const int ka_l = row_basis<P, TAB>(s, a0, nr, ua, Nu_l, a0 == row0 ? rpre : nullptr);
         int eb = 0;  // rows in the current dL/dNu batch
         for (int t = 0; t < nr; ++t) {
             const float3 g = gn;
@@ -878,15 +941,15 @@ __device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, B
     }
 }
 
-template <int P, int QM>
+template <int P, int QM, bool TAB = false>
 __device__ __forceinline__ void bwd_rows(const Surf& s, BwdState<QM>& st, int col0, int row0, int row1, float u0,
                                          const float* __restrict__ gpts, SlotView out, BwdLds* L,
-                                         unsigned mask) {
+                                         unsigned mask, const RowPre<P>* rpre = nullptr) {
     Block bk = make_block(L->blk, st.j0, st.ncols, P);
     if (bk.on)
-        bwd_rows_impl<P, QM, true>(s, st, bk, col0, row0, row1, u0, gpts, out, L, mask);
+        bwd_rows_impl<P, QM, true, TAB>(s, st, bk, col0, row0, row1, u0, gpts, out, L, mask, rpre);
     else
-        bwd_rows_impl<P, QM, false>(s, st, bk, col0, row0, row1, u0, gpts, out, L, mask);
+        bwd_rows_impl<P, QM, false, TAB>(s, st, bk, col0, row0, row1, u0, gpts, out, L, mask, rpre);
 }
 
 // Stage the tile's first inputs (knots into LDS); returns the surface view
@@ -900,14 +963,20 @@ __device__ __forceinline__ Surf bwd_stage(const Surf& sg, int p, int q, int col0
     return s;
 }
 
-template <int P, int QM>
+template <int P, int QM, bool TAB = false>
 __device__ __forceinline__ void bwd_tile(const Surf& sg, int q, int col0, int row0, int row1,
                                          const float* __restrict__ gpts, SlotView out, BwdLds* L, unsigned mask) {
     TileIn in;
+    ColPre<QM> cpre;
+    RowPre<P> rpre;
+    if constexpr (TAB) {
+        col_prefetch<QM>(sg, q, col0, cpre);
+        row_prefetch<P>(sg, row0, row1, rpre);
+    }
     const Surf s = bwd_stage(sg, P, q, col0, row0, row1, L, in);
     BwdState<QM> st;
-    bwd_columns<QM>(s, q, col0, in.v, st, L);
-    bwd_rows<P, QM>(s, st, col0, row0, row1, in.u0, gpts, out, L, mask);
+    bwd_columns<QM, TAB>(s, q, col0, in.v, st, L, &cpre);
+    bwd_rows<P, QM, TAB>(s, st, col0, row0, row1, in.u0, gpts, out, L, mask, &rpre);
 }
 
 // --------------------------------------------------------------------------

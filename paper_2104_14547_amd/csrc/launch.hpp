@@ -14,7 +14,15 @@ struct UniformArgs {
     int ntiles;
     unsigned flags;
     int* err;
+    // fixed-knot tables (NULL: spans and basis are evaluated); per surface
+    // at tab_u + s * tab_u_stride (stride 0: one table for the batch)
+    const char *tab_u, *tab_v;
+    size_t tab_u_stride, tab_v_stride;
 };
+
+// Byte offset of the basis rows in a fixed-knot table of n samples (the
+// n int32 spans come first).
+__host__ __device__ inline size_t basis_table_split(int n) { return ((size_t)n * 4 + 255) & ~size_t(255); }
 
 // One surface of a ragged batch, as the device sees it.
 struct DevDesc {

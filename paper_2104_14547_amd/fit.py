@@ -12,6 +12,19 @@ with the inverse square of a span, stays finite).  The projection is a
 running maximum and a running minimum, so each knot keeps its index and its
 Adam moments.
 
+With fixed knots (``train_knots=False``) the spans and basis values of the
+sample grid are computed once into tables (the fixed-knot B-spline layer
+with a precomputed basis) and every step reads them
+(``nurbs_surface_fwd_tab`` / ``nurbs_surface_bwd_tab``) unless
+``cached_basis=False``.
+
+The fit owns a library context whose tiling (sample points per forward and
+backward tile) is chosen at construction by timing the candidates on the
+problem itself (``tiling="auto"``): one surface of 512 x 512 samples makes
+only 16 tiles at the default 16384 points per tile, far too few waves for
+the chip.  The summation order, and so the bits of the result, depend on
+the tiling only.
+
 With ``graph=True`` the whole step (both library launches, the loss gradient,
 Adam and the projections) is captured once in a HIP graph and replayed, so a
 step costs one graph launch.  Every buffer is allocated before capture.
@@ -21,7 +34,11 @@ from __future__ import annotations
 import torch
 
 from . import _native as N
-from .api import surface_bwd, surface_fwd
+from .api import Context, basis_table, surface_bwd, surface_bwd_tab, surface_fwd, surface_fwd_tab
+
+# points per tile tried by the tiling search: a single surface needs small
+# tiles to occupy the chip, a large one amortises the per-tile set-up
+FIT_TILE_CANDIDATES = (256, 512, 1024, 2048, 4096, 16384)
 
 
 def project_knots(inner, ramp, top: float):
@@ -42,7 +59,8 @@ class SurfaceFit:
     """
 
     def __init__(self, ctrl, w, ku, kv, p: int, q: int, us, vs, target, lr: float = 1e-2,
-                 train_knots: bool = True, w_min: float = 1e-3, knot_gap: float = 1e-3, graph: bool = True):
+                 train_knots: bool = True, w_min: float = 1e-3, knot_gap: float = 1e-3, graph: bool = True,
+                 cached_basis: bool = True, tiling="auto"):
         self.p, self.q = int(p), int(q)
         self.ctrl = ctrl.detach().clone().contiguous()
         self.w = w.detach().clone().contiguous()
@@ -66,8 +84,18 @@ class SurfaceFit:
             self.mask |= N.NURBS_GRAD_KU | N.NURBS_GRAD_KV
             params += [self.ku, self.kv]
         self.params = params
+        # fixed knots: spans and basis of the sample grid, computed once
+        self.tabs = None
+        if not self.train_knots and cached_basis:
+            self.tabs = (basis_table(self.ku, self.p, self.us), basis_table(self.kv, self.q, self.vs))
         self.pts = torch.empty_like(self.target)
         self.g = torch.empty_like(self.target)
+        self.ctx = Context(ctrl.device.index)
+        if tiling == "auto":
+            tiling = self._tune_tiling()
+        if tiling:
+            self.ctx.set_tiling(*tiling)
+        self.tiling = getattr(self.ctx, "tiling", (16384, 16384))
         for t in params:
             t.grad = torch.zeros_like(t)
         # capturable in both modes, so eager and graph steps run the same arithmetic
@@ -77,13 +105,53 @@ class SurfaceFit:
         if graph:
             self._capture()
 
+    def _fwd(self):
+        if self.tabs is not None:
+            tu, tv = self.tabs
+            surface_fwd_tab(self.ctrl, self.w, self.ku, self.kv, self.p, self.q, self.us, self.vs, tu, tv,
+                            out=self.pts, ctx=self.ctx)
+        else:
+            surface_fwd(self.ctrl, self.w, self.ku, self.kv, self.p, self.q, self.us, self.vs, out=self.pts,
+                        ctx=self.ctx)
+
+    def _bwd(self):
+        if self.tabs is not None:
+            gc, gw = surface_bwd_tab(self.ctrl, self.w, self.ku, self.kv, self.p, self.q, self.us, self.vs,
+                                     *self.tabs, self.g, mask=self.mask, ctx=self.ctx)
+            return gc, gw, None, None
+        return surface_bwd(self.ctrl, self.w, self.ku, self.kv, self.p, self.q, self.us, self.vs, self.g,
+                           mask=self.mask, ctx=self.ctx)
+
+    def _tune_tiling(self, reps: int = 5):
+        """The forward and the backward tile sizes that run fastest on this
+        problem (HIP events around each call, median of ``reps``)."""
+        self.g.zero_()
+        best = {}
+        for cand in FIT_TILE_CANDIDATES:
+            self.ctx.set_tiling(cand, cand)
+            self._fwd()
+            self._bwd()
+            times = {"fwd": [], "bwd": []}
+            for _ in range(reps):
+                for k, fn in (("fwd", self._fwd), ("bwd", self._bwd)):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    fn()
+                    b.record()
+                    times[k].append((a, b))
+            torch.cuda.synchronize()
+            for k, ev in times.items():
+                t = sorted(x.elapsed_time(y) for x, y in ev)[len(ev) // 2]
+                if k not in best or t < best[k][0]:
+                    best[k] = (t, cand)
+        return best["fwd"][1], best["bwd"][1]
+
     # -- one step, written with preallocated tensors only ------------------
     def _step_body(self):
-        surface_fwd(self.ctrl, self.w, self.ku, self.kv, self.p, self.q, self.us, self.vs, out=self.pts)
+        self._fwd()
         torch.sub(self.pts, self.target, out=self.g)
         self.g.mul_(2.0)
-        gc, gw, gu, gv = surface_bwd(self.ctrl, self.w, self.ku, self.kv, self.p, self.q, self.us, self.vs,
-                                     self.g, mask=self.mask)
+        gc, gw, gu, gv = self._bwd()
         self.ctrl.grad.copy_(gc)
         self.w.grad.copy_(gw)
         if self.train_knots:
@@ -136,5 +204,5 @@ class SurfaceFit:
     @torch.no_grad()
     def loss(self) -> float:
         """L = sum ||S - T||^2 at the current parameters (evaluated eagerly)."""
-        S = surface_fwd(self.ctrl, self.w, self.ku, self.kv, self.p, self.q, self.us, self.vs)
+        S = surface_fwd(self.ctrl, self.w, self.ku, self.kv, self.p, self.q, self.us, self.vs, ctx=self.ctx)
         return float(((S.double() - self.target.double()) ** 2).sum())

@@ -14,6 +14,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from paper_2104_14547_amd import workloads as W  # noqa: E402
+from paper_2104_14547_amd import fit as nd_fit  # noqa: E402
 from paper_2104_14547_amd.fit import SurfaceFit  # noqa: E402
 from oracle import oracle as O  # noqa: E402
 
@@ -35,9 +36,11 @@ def small_problem(nc=12, ns=48):
     return b.surface(0)
 
 
-def make_fit(s, graph, train_knots=True):
+def make_fit(s, graph, train_knots=True, tiling=(1024, 1024)):
+    # a fixed tiling where two fits are compared bit for bit (the automatic
+    # choice is timed, so two fits could pick different tilings)
     return SurfaceFit(T(s["ctrl"]), T(s["w"]), T(s["ku"]), T(s["kv"]), s["p"], s["q"], T(s["us"]), T(s["vs"]),
-                      T(s["target"]), lr=LR, train_knots=train_knots, graph=graph)
+                      T(s["target"]), lr=LR, train_knots=train_knots, graph=graph, tiling=tiling)
 
 
 def state(f):
@@ -107,7 +110,8 @@ def test_first_steps_follow_fp64_fit():
     s = small_problem()
     steps = 10
     ref = oracle_fit(s, steps)
-    f = make_fit(s, graph=True)
+    f = make_fit(s, graph=True, tiling="auto")
+    assert f.tiling[0] in nd_fit.FIT_TILE_CANDIDATES and f.tiling[1] in nd_fit.FIT_TILE_CANDIDATES
     got = [f.loss()]
     for _ in range(steps):
         f.step()
