@@ -178,7 +178,7 @@ def served_leg(batch, n_req: int, seed: int = 4):
             st["load"] = f
             out["rates"].append(st)
         out["batches"] = srv.batches
-    n_plain = min(n_req, 400)
+    n_plain = min(n_req, 2000)
     plain = {"requests_per_rate": n_plain, "rates": []}
     with PlainServer(batch) as ps:
         run_load(ps, reqs[:20], rate=None)
@@ -537,7 +537,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="default tiles instead of the autotuned ones")
     ap.add_argument("--tiles", default="", metavar="FWD,BWD",
                     help="fixed sample points per forward,backward tile (skips the autotuner)")
-    ap.add_argument("--served-requests", type=int, default=3000,
+    ap.add_argument("--served-requests", type=int, default=20000,
                     help="requests per arrival rate in the served leg (0: skip it)")
     ap.add_argument("--fit-steps", type=int, default=500, help="steps of the fitting leg (0: skip it)")
     ap.add_argument("--uniform-steps", type=int, default=20,

@@ -34,6 +34,7 @@ from __future__ import annotations
 import collections
 import ctypes
 import gc
+import sys
 import threading
 import time
 from concurrent.futures import Future
@@ -46,6 +47,12 @@ from . import _native as N
 from .api import Context, NurbsError, _check, _ptr
 
 _ALIGN = 256
+
+# nurbs_desc as a numpy record type (six int32, then seven int64)
+_DESC_DTYPE = np.dtype([(n, np.int32) for n in ("p", "q", "nu_c", "nv_c", "nu_s", "nv_s")] +
+                       [(n, np.int64) for n in ("ctrl_off", "w_off", "ku_off", "kv_off", "us_off", "vs_off",
+                                                "pts_off")], align=True)
+assert _DESC_DTYPE.itemsize == ctypes.sizeof(N.nurbs_desc)
 
 
 def _al(x: int) -> int:
@@ -159,6 +166,17 @@ class Server:
         self.next_id = 0
         self.completed = []  # (rid, latency, points) for statistics
         self.batches = 0
+        # per surface, once: the flat indices of its four gradient blocks in
+        # the slot's gradient buffer (a batch's gather index is their
+        # concatenation) and the counts of those blocks
+        self._gidx, self._gcnt = [], []
+        for surf in range(len(self.shapes)):
+            cnts = self._grad_elems(surf)
+            self._gcnt.append(cnts)
+            self._gidx.append(np.concatenate([np.arange(int(self.grad_base[k] + self.offs[surf, k]),
+                                                        int(self.grad_base[k] + self.offs[surf, k]) + c,
+                                                        dtype=np.int64) for k, c in enumerate(cnts)]))
+        self._size_cache = {}
 
     # -- request sizing -----------------------------------------------------
     def _desc(self, surf, nu_s, nv_s, us_off, vs_off, pts_off):
@@ -176,16 +194,21 @@ class Server:
 
     def _size(self, req: Request):
         nu_s, nv_s = len(req.us), len(req.vs)
-        arr = (N.nurbs_desc * 1)(self._desc(req.surf, nu_s, nv_s, 0, 0, 0))
-        tb, wb = ctypes.c_size_t(), ctypes.c_size_t()
-        _check(N.lib().nurbs_plan_create_in(self.ctx.handle, arr, 1, 0, None, 0, None, None, ctypes.byref(tb),
-                                            ctypes.byref(wb)), self.ctx.handle)
-        req.ws_bytes, req.table_bytes = int(wb.value), int(tb.value)
-        npts = nu_s * nv_s
-        outs = sum(self._grad_elems(req.surf))
-        # us, vs, target, points, dL/dS, gradient index and packed outputs, workspace, tables
-        req.nbytes = (_al(4 * (nu_s + nv_s)) + 3 * _al(12 * npts) + _al(8 * outs) + _al(4 * outs) +
-                      _al(req.ws_bytes) + req.table_bytes)
+        key = (req.surf, nu_s, nv_s)
+        hit = self._size_cache.get(key)
+        if hit is None:
+            # the plan's sizes depend on the shapes only: asked once per shape
+            arr = (N.nurbs_desc * 1)(self._desc(req.surf, nu_s, nv_s, 0, 0, 0))
+            tb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+            _check(N.lib().nurbs_plan_create_in(self.ctx.handle, arr, 1, 0, None, 0, None, None, ctypes.byref(tb),
+                                                ctypes.byref(wb)), self.ctx.handle)
+            npts = nu_s * nv_s
+            outs = sum(self._gcnt[req.surf])
+            # us, vs, target, points, dL/dS, gradient index and packed outputs, workspace, tables
+            nbytes = (_al(4 * (nu_s + nv_s)) + 3 * _al(12 * npts) + _al(8 * outs) + _al(4 * outs) +
+                      _al(int(wb.value)) + int(tb.value))
+            hit = self._size_cache[key] = (int(wb.value), int(tb.value), nbytes)
+        req.ws_bytes, req.table_bytes, req.nbytes = hit
 
     # -- public API ---------------------------------------------------------
     def submit(self, surf: int, us, vs, target, t_arrival: float | None = None) -> Future:
@@ -265,10 +288,13 @@ class Server:
             lay[name] = (off, int(nbytes))
             off += _al(nbytes)
 
-        n_uv = sum(len(r.us) + len(r.vs) for r in batch)
-        n_pts = sum(len(r.us) * len(r.vs) for r in batch)
-        gsizes = [self._grad_elems(r.surf) for r in batch]
-        n_out = sum(sum(g) for g in gsizes)
+        surfs = np.fromiter((r.surf for r in batch), np.int64, n)
+        nus = np.fromiter((len(r.us) for r in batch), np.int64, n)
+        nvs = np.fromiter((len(r.vs) for r in batch), np.int64, n)
+        npts = nus * nvs
+        n_uv, n_pts = int((nus + nvs).sum()), int(npts.sum())
+        gsizes = [self._gcnt[sf] for sf in surfs]
+        n_out = int(sum(sum(g) for g in gsizes))
         ws_bytes = 256 + sum(r.ws_bytes - 256 for r in batch)
         region("uv", 4 * n_uv)
         region("target", 12 * n_pts)
@@ -290,22 +316,23 @@ class Server:
             o, nb = lay[name]
             return s.arena[o:o + nb].view(dtype)
 
-        uv_h, tg_h, ix_h = hview("uv", np.float32), hview("target", np.float32), hview("index", np.int64)
-        descs = (N.nurbs_desc * n)()
-        cu = cp = co = 0
-        for i, r in enumerate(batch):
-            nu_s, nv_s = len(r.us), len(r.vs)
-            uv_h[cu:cu + nu_s] = r.us
-            uv_h[cu + nu_s:cu + nu_s + nv_s] = r.vs
-            tg_h[3 * cp:3 * (cp + nu_s * nv_s)] = r.target.reshape(-1)
-            descs[i] = self._desc(r.surf, nu_s, nv_s, cu, cu + nu_s, 3 * cp)
-            o = self.offs[r.surf]
-            for k, cnt in enumerate(gsizes[i]):
-                start = int(self.grad_base[k] + o[k])
-                ix_h[co:co + cnt] = np.arange(start, start + cnt, dtype=np.int64)
-                co += cnt
-            cu += nu_s + nv_s
-            cp += nu_s * nv_s
+        # packing: one concatenation per array, straight into the pinned mirror
+        np.concatenate([x for r in batch for x in (r.us, r.vs)], out=hview("uv", np.float32))
+        np.concatenate([r.target.reshape(-1) for r in batch], out=hview("target", np.float32))
+        np.concatenate([self._gidx[sf] for sf in surfs], out=hview("index", np.int64))
+        # descriptors, filled column-wise in a record array laid out as nurbs_desc
+        D = np.zeros(n, _DESC_DTYPE)
+        sh = self.shapes[surfs]
+        for k, name in enumerate(("p", "q", "nu_c", "nv_c")):
+            D[name] = sh[:, k]
+        D["nu_s"], D["nv_s"] = nus, nvs
+        o = self.offs[surfs]
+        for k, name in enumerate(("ctrl_off", "w_off", "ku_off", "kv_off")):
+            D[name] = o[:, k]
+        uv_start = np.concatenate([[0], np.cumsum(nus + nvs)[:-1]])
+        D["us_off"], D["vs_off"] = uv_start, uv_start + nus
+        D["pts_off"] = 3 * np.concatenate([[0], np.cumsum(npts)[:-1]])
+        descs = D.ctypes.data_as(ctypes.POINTER(N.nurbs_desc))
         st = s.stream
         with torch.cuda.stream(st):
             up = lay["index"][0] + lay["index"][1]  # uv, target and index are contiguous at the front
@@ -316,6 +343,7 @@ class Server:
             _check(N.lib().nurbs_plan_create_in(self.ctx.handle, descs, n, 0, _ptr(s.arena) + o_t, n_t,
                                                 st.cuda_stream, ctypes.byref(plan), ctypes.byref(tb),
                                                 ctypes.byref(wb)), self.ctx.handle)
+            s.descs = D  # the plan copies the descriptors, but keep them until the batch is done
             s.plan = plan
             uv = dview("uv", torch.float32)
             pts, g = dview("pts", torch.float32), dview("g", torch.float32)
@@ -350,17 +378,19 @@ class Server:
         pts = H[o:o + nb].view(np.float32)
         o, nb = lay["out"]
         out = H[o:o + nb].view(np.float32)
+        # one copy of each packed array out of the pinned mirror, then views
+        pts = pts.copy()
+        out = out.copy()
         cp = co = 0
         for r, gs in zip(s.batch, gsizes):
             nu_s, nv_s = len(r.us), len(r.vs)
-            S = pts[3 * cp:3 * (cp + nu_s * nv_s)].reshape(nu_s, nv_s, 3).copy()
-            parts = []
-            for cnt in gs:
-                parts.append(out[co:co + cnt].copy())
-                co += cnt
+            S = pts[3 * cp:3 * (cp + nu_s * nv_s)].reshape(nu_s, nv_s, 3)
+            c0, c1, c2, c3 = gs
             p, q, nu_c, nv_c = (int(x) for x in self.shapes[r.surf, :4])
-            res = Result(S, parts[0].reshape(nu_c, nv_c, 3), parts[1].reshape(nu_c, nv_c), parts[2], parts[3],
+            res = Result(S, out[co:co + c0].reshape(nu_c, nv_c, 3), out[co + c0:co + c0 + c1].reshape(nu_c, nv_c),
+                         out[co + c0 + c1:co + c0 + c1 + c2], out[co + c0 + c1 + c2:co + c0 + c1 + c2 + c3],
                          latency=now - r.t_arrival)
+            co += c0 + c1 + c2 + c3
             self.completed.append((r.rid, res.latency, nu_s * nv_s))
             r.future.set_result(res)
             cp += nu_s * nv_s
@@ -477,6 +507,11 @@ def run_load(server, requests, rate: float | None, seed: int = 5):
     gc.collect()
     gc_was_on = gc.isenabled()
     gc.disable()
+    # the client (this thread) and the serving thread share the interpreter
+    # lock; at the default 5 ms switch interval a busy client can hold the
+    # server off for whole milliseconds, which shows up as tail latency
+    switch = sys.getswitchinterval()
+    sys.setswitchinterval(1e-4)
     try:
         t0 = time.perf_counter()
         arrivals = t0 + np.cumsum(gaps)
@@ -489,6 +524,7 @@ def run_load(server, requests, rate: float | None, seed: int = 5):
         results = [f.result() for f in futs]
         t1 = time.perf_counter()
     finally:
+        sys.setswitchinterval(switch)
         if gc_was_on:
             gc.enable()
     lat = np.array([r.latency for r in results])
