@@ -68,9 +68,10 @@ def algorithmic_bytes(shapes):
             "fin": 16 * cps + 4 * kn}
 
 
-def traffic_for(kernel: str, workload: str, tiles: dict):
+def traffic_for(kernel: str, workload: str, chosen: dict):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel sources at the same tiling; else None."""
+    were taken on the current kernel sources with the same schedule and the
+    same tile size for this kernel's direction; else None."""
     path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -78,12 +79,11 @@ def traffic_for(kernel: str, workload: str, tiles: dict):
         rec = json.load(fh)
     if rec.get("kernel_source_digest") != kernel_source_digest():
         return None
-    if rec.get("tiles") != tiles:
-        return None
-    k = rec.get("kernels", {}).get(kernel)
-    if not k:
-        return None
-    return k.get("hbm_bytes_per_launch")
+    tile = chosen["fwd_tile_points"] if kernel == "k_fwd_plan" else chosen["bwd_tile_points"]
+    for r in rec.get("records", []):
+        if r["kernel"] == kernel and r["tile_points"] == tile and r["schedule"] == chosen.get("schedule"):
+            return r["hbm_bytes_per_launch"]
+    return None
 
 
 def timed_steps(torch, step, n: int, flush=None):
@@ -537,6 +537,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="default tiles instead of the autotuned ones")
     ap.add_argument("--tiles", default="", metavar="FWD,BWD",
                     help="fixed sample points per forward,backward tile (skips the autotuner)")
+    ap.add_argument("--schedule", default="dynamic", choices=["dynamic", "static"],
+                    help="tile schedule with --tiles")
     ap.add_argument("--served-requests", type=int, default=20000,
                     help="requests per arrival rate in the served leg (0: skip it)")
     ap.add_argument("--fit-steps", type=int, default=500, help="steps of the fitting leg (0: skip it)")
@@ -579,12 +581,14 @@ def main():
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     inputs = [T(getattr(batch, k)) for k in ("ctrl", "w", "ku", "kv", "us", "vs")]
     upstream = T(batch.upstream)
+    sched = {"dynamic": nd.api.N.NURBS_SCHED_DYNAMIC, "static": nd.api.N.NURBS_SCHED_STATIC}
     if args.tiles:
         tf, tb = (int(x) for x in args.tiles.split(","))
         ctx = nd.api.Context(0)
         ctx.set_tiling(tf, tb)
+        ctx.set_schedule(sched[args.schedule])
         plan = nd.SurfaceBatch(batch.shapes, batch.offsets, device=0, ctx=ctx)
-        tune = {"chosen": {"fwd_tile_points": tf, "bwd_tile_points": tb}, "fixed": True}
+        tune = {"chosen": {"schedule": args.schedule, "fwd_tile_points": tf, "bwd_tile_points": tb}, "fixed": True}
     elif args.no_autotune:
         plan, tune = nd.SurfaceBatch(batch.shapes, batch.offsets, device=0), None
     else:
@@ -628,7 +632,7 @@ def main():
     achieved = ab[dom] / (avg[dom] * 1e-3) / 1e9
     kernels = {names[k]: {"avg_ms": avg[k], "algorithmic_bytes": ab[k],
                           "achieved_GBs": ab[k] / (avg[k] * 1e-3) / 1e9} for k in avg}
-    chosen = tune["chosen"] if tune else {"fwd_tile_points": 16384, "bwd_tile_points": 16384}
+    chosen = tune["chosen"] if tune else {"schedule": "dynamic", "fwd_tile_points": 16384, "bwd_tile_points": 16384}
     traffic = traffic_for(names[dom], args.workload, chosen)
 
     result = {

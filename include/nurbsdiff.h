@@ -86,6 +86,15 @@ extern "C" {
 /* flags */
 #define NURBS_VALIDATE 1u /* run the device-side data checks */
 
+/* bytes at the start of a plan's workspace that are not tile slots: the
+ * error word and the dynamic schedule's tile counters (a plan forward needs
+ * this much workspace under the dynamic schedule) */
+#define NURBS_PLAN_WS_HEADER 4352
+
+/* tile schedules of the ragged-batch plans (nurbs_ctx_set_schedule) */
+#define NURBS_SCHED_STATIC 0  /* tiles assigned to waves when the plan is built (default) */
+#define NURBS_SCHED_DYNAMIC 1 /* waves take tiles from counters at run time */
+
 typedef struct nurbs_ctx nurbs_ctx;
 typedef struct nurbs_plan nurbs_plan;
 
@@ -121,6 +130,21 @@ int nurbs_ctx_set_knot_sigma(nurbs_ctx *ctx, float sigma);
  * change the summation order of the backward within the tolerances.  An
  * autotuner picks these per workload. */
 int nurbs_ctx_set_tiling(nurbs_ctx *ctx, int fwd_tile_points, int bwd_tile_points);
+/* How plans created later on this context hand tiles to their persistent
+ * waves (Alg. Forward / Alg. Backward run all tiles in parallel; this is
+ * only their order on the GPU):
+ *   NURBS_SCHED_STATIC  : each wave runs a list fixed when the plan is built
+ *                         (longest-processing-time greedy on a cost model);
+ *                         the default;
+ *   NURBS_SCHED_DYNAMIC : the tiles are ordered by decreasing estimated cost
+ *                         and dealt to 16 queues; each wave runs one tile of
+ *                         its queue and then takes the next from the queue's
+ *                         counter in the workspace header (one integer
+ *                         atomic per tile).  Plan forwards then need
+ *                         NURBS_PLAN_WS_HEADER bytes of workspace.
+ * Both give bit-identical results (every tile writes its own slot).
+ * NURBS_EINVAL for any other value. */
+int nurbs_ctx_set_schedule(nurbs_ctx *ctx, int schedule);
 const char *nurbs_status_string(int status);
 /* Text of the last error raised on this context (never NULL). */
 const char *nurbs_last_error(nurbs_ctx *ctx);
@@ -397,6 +421,10 @@ int nurbs_plan_destroy(nurbs_plan *plan);
 /* Tile statistics of a plan: number of forward / backward tiles. */
 int nurbs_plan_info(nurbs_plan *plan, int *fwd_tiles, int *bwd_tiles, int *grid);
 
+/* ws / ws_bytes: the plan's workspace (at least the reported size for the
+ * backward; for a forward, NURBS_PLAN_WS_HEADER bytes under the dynamic
+ * schedule -- its tile counters -- or 256 under NURBS_VALIDATE -- the error
+ * word).  Calls that may overlap need workspaces of their own. */
 int nurbs_plan_fwd(nurbs_plan *plan, const float *ctrl, const float *w,
                    const float *ku, const float *kv, const float *us,
                    const float *vs, float *pts, void *ws, size_t ws_bytes,

@@ -29,6 +29,9 @@ NURBS_GRAD_KU = 4
 NURBS_GRAD_KV = 8
 NURBS_GRAD_ALL = 15
 NURBS_VALIDATE = 1
+NURBS_PLAN_WS_HEADER = 4352
+NURBS_SCHED_STATIC = 0
+NURBS_SCHED_DYNAMIC = 1
 NURBS_MAX_DEGREE = 7
 NURBS_MAX_KNOTS = 256
 
@@ -46,6 +49,7 @@ EXPORTS = (
     "nurbs_chamfer_ws_bytes", "nurbs_nearest", "nurbs_chamfer",
     "nurbs_surface_uv_ws_bytes", "nurbs_surface_uv_fwd", "nurbs_surface_uv_bwd",
     "nurbs_basis_table_bytes", "nurbs_basis_table_build", "nurbs_surface_fwd_tab", "nurbs_surface_bwd_tab",
+    "nurbs_ctx_set_schedule",
 )
 
 
@@ -69,6 +73,7 @@ _SIGS = {
     "nurbs_ctx_set_flags": (_i, [_vp, _u]),
     "nurbs_ctx_set_knot_sigma": (_i, [_vp, ctypes.c_float]),
     "nurbs_ctx_set_tiling": (_i, [_vp, _i, _i]),
+    "nurbs_ctx_set_schedule": (_i, [_vp, _i]),
     "nurbs_status_string": (ctypes.c_char_p, [_i]),
     "nurbs_last_error": (ctypes.c_char_p, [_vp]),
     "nurbs_ctx_device_info": (_i, [_vp, _ip, _ip]),

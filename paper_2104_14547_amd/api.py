@@ -78,6 +78,12 @@ class Context:
         _check(N.lib().nurbs_ctx_set_tiling(self.handle, int(fwd_tile_points), int(bwd_tile_points)), self.handle)
         self.tiling = (int(fwd_tile_points) or 16384, int(bwd_tile_points) or 16384)
 
+    def set_schedule(self, schedule: int):
+        """Tile schedule of plans created later on this context
+        (NURBS_SCHED_DYNAMIC, the default, or NURBS_SCHED_STATIC)."""
+        _check(N.lib().nurbs_ctx_set_schedule(self.handle, int(schedule)), self.handle)
+        self.schedule = int(schedule)
+
     def device_info(self):
         cus, wave = ctypes.c_int(), ctypes.c_int()
         _check(N.lib().nurbs_ctx_device_info(self.handle, ctypes.byref(cus), ctypes.byref(wave)), self.handle)
@@ -755,27 +761,33 @@ def basis(knots, p: int, x):
 # tile autotuning
 # --------------------------------------------------------------------------
 
-TILE_CANDIDATES = (4096, 8192, 16384, 32768, 65536)
+TILE_CANDIDATES = (2048, 4096, 8192, 16384, 65536)
+SCHEDULES = (N.NURBS_SCHED_DYNAMIC, N.NURBS_SCHED_STATIC)
 
 
 def autotune(shapes, offsets, inputs, upstream, device: int | None = None, candidates=TILE_CANDIDATES,
-             reps: int = 5, validate: bool = False):
-    """Pick the forward and backward tile sizes for a ragged batch by timing.
+             schedules=SCHEDULES, reps: int = 5, validate: bool = False):
+    """Pick the tile schedule and the forward and backward tile sizes for a
+    ragged batch by timing.
 
-    Every candidate target (sample points per tile) is timed on the batch
-    itself -- the forward and the backward (with its finalize) separately,
-    ``reps`` calls each after a warm-up call, with HIP events on the plan's
-    stream -- and the fastest of each direction is kept.  Returns
-    ``(plan, report)``: a SurfaceBatch built with the chosen tiling (on a
-    context of its own) and the timings in ms per candidate."""
+    Every (schedule, target sample points per tile) pair is timed on the
+    batch itself -- the forward and the backward (with its finalize)
+    separately, ``reps`` calls each after a warm-up call, with HIP events on
+    the plan's stream -- and the fastest of each direction is kept (the
+    schedule by the sum of the two).  Returns ``(plan, report)``: a
+    SurfaceBatch built with the chosen settings (on a context of its own)
+    and the timings in ms per candidate, keyed "<schedule>:<points>"."""
     ctrl, w, ku, kv, us, vs = inputs
     dev = ctrl.device
     report = {"fwd": {}, "bwd": {}}
     pts = None
     grads = (torch.empty_like(ctrl), torch.empty_like(w), torch.empty_like(ku), torch.empty_like(kv))
-    for cand in candidates:
+    names = {N.NURBS_SCHED_DYNAMIC: "dynamic", N.NURBS_SCHED_STATIC: "static"}
+    for sched in schedules:
+      for cand in candidates:
         ctx = Context(device, validate=validate)
         ctx.set_tiling(cand, cand)
+        ctx.set_schedule(sched)
         plan = SurfaceBatch(shapes, offsets, device=device, validate=validate, ctx=ctx)
         if pts is None:
             pts = torch.empty(plan.n_pts_floats, dtype=torch.float32, device=dev)
@@ -790,13 +802,19 @@ def autotune(shapes, offsets, inputs, upstream, device: int | None = None, candi
         torch.cuda.synchronize(dev)
         f, b, z = plan.read_timing()
         plan.set_timing(0)
-        report["fwd"][cand] = float(np.median(f))
-        report["bwd"][cand] = float(np.median(b + z))
+        key = f"{names[sched]}:{cand}"
+        report["fwd"][key] = float(np.median(f))
+        report["bwd"][key] = float(np.median(b + z))
         plan.close()
         del plan
-    best_f = min(report["fwd"], key=report["fwd"].get)
-    best_b = min(report["bwd"], key=report["bwd"].get)
+    # one schedule for both directions (a plan has one), then the best tiling of each
+    best_sched = min(schedules, key=lambda sc: min(v for k, v in report["fwd"].items() if k.startswith(names[sc]))
+                     + min(v for k, v in report["bwd"].items() if k.startswith(names[sc])))
+    pref = names[best_sched] + ":"
+    best_f = int(min((k for k in report["fwd"] if k.startswith(pref)), key=report["fwd"].get).split(":")[1])
+    best_b = int(min((k for k in report["bwd"] if k.startswith(pref)), key=report["bwd"].get).split(":")[1])
     ctx = Context(device, validate=validate)
     ctx.set_tiling(best_f, best_b)
-    report["chosen"] = {"fwd_tile_points": best_f, "bwd_tile_points": best_b}
+    ctx.set_schedule(best_sched)
+    report["chosen"] = {"schedule": names[best_sched], "fwd_tile_points": best_f, "bwd_tile_points": best_b}
     return SurfaceBatch(shapes, offsets, device=device, validate=validate, ctx=ctx), report

@@ -25,6 +25,7 @@ struct nurbs_ctx {
     int occ[2][2] = {{0, 0}, {0, 0}};  // persistent-kernel workgroups per CU: [class d5, d7][fwd, bwd]
     int fwd_tile_pts = 16384;          // target points per forward / backward tile
     int bwd_tile_pts = 16384;
+    int schedule = NURBS_SCHED_STATIC;  // of plans created on this context
     std::string err;
 };
 
@@ -50,6 +51,7 @@ struct nurbs_plan {
     size_t ws_bytes = 0;
     int max_nU = 0, max_nV = 0;
     int maxd = 5;  // degree class of the persistent kernels (5 or 7)
+    int schedule = NURBS_SCHED_STATIC;
     std::vector<char> staging;  // host copy of the tables (plans made in caller memory)
     // tracing: event ring per direction (2 events per forward, 3 per backward)
     int trace_slots = 0;
@@ -175,6 +177,14 @@ int nurbs_ctx_set_tiling(nurbs_ctx* ctx, int fwd_tile_points, int bwd_tile_point
     return NURBS_OK;
 }
 
+int nurbs_ctx_set_schedule(nurbs_ctx* ctx, int schedule) {
+    if (!ctx) return fail(nullptr, NURBS_EINVAL, "ctx is NULL");
+    if (schedule != NURBS_SCHED_STATIC && schedule != NURBS_SCHED_DYNAMIC)
+        return fail(ctx, NURBS_EINVAL, "schedule must be NURBS_SCHED_STATIC or NURBS_SCHED_DYNAMIC");
+    ctx->schedule = schedule;
+    return NURBS_OK;
+}
+
 const char* nurbs_last_error(nurbs_ctx* ctx) { return ctx ? ctx->err.c_str() : g_noctx_err.c_str(); }
 
 int nurbs_ctx_device_info(nurbs_ctx* ctx, int* num_cus, int* wave_size) {
@@ -210,6 +220,12 @@ UniformGeom uniform_geom(const nurbs_ctx* c, int B, int p, int q, int nu_c, int 
 }
 
 constexpr size_t kWsHeader = 256;  // error word + padding
+// plan workspaces: the 256-byte header, then the dynamic schedule's tile
+// counters of the forward and of the backward (kQueues each, 128 bytes apart)
+constexpr size_t kQueueFwd = kWsHeader;
+constexpr size_t kQueueBwd = kQueueFwd + 4 * (size_t)kQueues * kQueueStride;
+constexpr size_t kPlanHeader = kQueueBwd + 4 * (size_t)kQueues * kQueueStride;
+static_assert(kPlanHeader == NURBS_PLAN_WS_HEADER, "plan workspace header");
 
 int uniform_common(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, int nu_s, int nv_s) {
     if (!ctx) return fail(nullptr, NURBS_EINVAL, "ctx is NULL");
@@ -824,12 +840,26 @@ double tile_cost(const nurbs_desc& d, int rows, bool bwd) {
     return 12.0 + rows * (1.0 + 0.25 * (d.p + 1)) + crow * (0.5 + 0.35 * (d.q + 1));
 }
 
-// Assign tiles to nw waves: longest first, each to the wave with the least
-// work so far.  Returns the tiles in wave order and the wave boundaries.
-void assign_waves(const std::vector<double>& cost, int nw, std::vector<int>& order, std::vector<int>& begin) {
+// Tiles by decreasing estimated cost (ties in tile order).
+std::vector<int> longest_first(const std::vector<double>& cost) {
     std::vector<int> idx(cost.size());
     std::iota(idx.begin(), idx.end(), 0);
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    return idx;
+}
+
+// Static schedule: assign tiles to nw waves, longest first, each to the wave
+// with the least work so far.  Returns the tiles in wave order and the wave
+// boundaries.  Dynamic schedule: the longest-first order itself (the waves
+// take tiles from it at run time); the boundaries are unused.
+void assign_waves(const std::vector<double>& cost, int nw, std::vector<int>& order, std::vector<int>& begin,
+                  bool dynamic) {
+    std::vector<int> idx = longest_first(cost);
+    if (dynamic) {
+        order = idx;
+        begin.assign(nw + 1, 0);
+        return;
+    }
     using Load = std::pair<double, int>;
     std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
     for (int w = 0; w < nw; ++w) heap.push({0.0, w});
@@ -879,6 +909,7 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
     pl->device = ctx->device;
     pl->n = n;
     pl->flags = flags;
+    pl->schedule = ctx->schedule;
     pl->host.assign(host, host + n);
 
     // tiles
@@ -899,7 +930,7 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
         const int rb = tile_rows(d.nu_s, d.nv_s, ctx->bwd_tile_pts);
         x.rows = rb;
         x.tile_first = (int)bt.size();
-        x.slot0 = (long long)(kWsHeader + slot_off);
+        x.slot0 = (long long)(kPlanHeader + slot_off);
         int cnt = 0;
         if (d.nu_s > 0 && d.nv_s > 0) {
             for (int r0 = 0; r0 < d.nu_s; r0 += rf)
@@ -910,7 +941,7 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
                 }
             for (int r0 = 0; r0 < d.nu_s; r0 += rb)
                 for (int cb = 0; cb < ncb; ++cb) {
-                    DevTile t{s, cb * kWave, r0, std::min(d.nu_s, r0 + rb), (long long)(kWsHeader + slot_off)};
+                    DevTile t{s, cb * kWave, r0, std::min(d.nu_s, r0 + rb), (long long)(kPlanHeader + slot_off)};
                     slot_off += align16(slot_bytes(d.p, d.q, d.nu_c, d.nv_c, rb));
                     bt.push_back(t);
                     bcost.push_back(tile_cost(d, t.row1 - t.row0, true));
@@ -923,7 +954,7 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
     }
     pl->nf = (int)ft.size();
     pl->nb = (int)bt.size();
-    pl->ws_bytes = kWsHeader + slot_off;
+    pl->ws_bytes = kPlanHeader + slot_off;
 
     // degree class and persistent grid: as many workgroups as fit at once
     int maxdeg = 1;
@@ -987,8 +1018,8 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
         return NURBS_OK;
     }
     std::vector<int> fo, fbeg, bo, bbeg;
-    assign_waves(fcost, (int)nwf, fo, fbeg);
-    assign_waves(bcost, (int)nwb, bo, bbeg);
+    assign_waves(fcost, (int)nwf, fo, fbeg, pl->schedule == NURBS_SCHED_DYNAMIC);
+    assign_waves(bcost, (int)nwb, bo, bbeg, pl->schedule == NURBS_SCHED_DYNAMIC);
     auto record = [&](const DevTile& t) {
         const DevDesc& x = dd[t.surf];
         ExecTile r;
@@ -1120,6 +1151,10 @@ PlanArgs plan_args(nurbs_plan* pl, bool bwd, void* ws, const float* ctrl, const 
     a.ntiles = bwd ? pl->nb : pl->nf;
     a.wave_begin = bwd ? pl->d_bbegin : pl->d_fbegin;
     a.nwaves = (bwd ? pl->grid_bwd : pl->grid_fwd) * kWavesPerWG;
+    // dynamic schedule: the tile counters live in the workspace header
+    a.queue = pl->schedule == NURBS_SCHED_DYNAMIC ? reinterpret_cast<int*>(reinterpret_cast<char*>(ws) +
+                                                                             (bwd ? kQueueBwd : kQueueFwd))
+                                                  : nullptr;
     a.flags = pl->flags;
     a.err = (pl->flags & NURBS_VALIDATE) ? reinterpret_cast<int*>(ws) : nullptr;
     a.ctrl = ctrl; a.w = w; a.ku = ku; a.kv = kv; a.us = us; a.vs = vs;
@@ -1137,6 +1172,9 @@ int nurbs_plan_fwd(nurbs_plan* pl, const float* ctrl, const float* w, const floa
     if (!ctrl || !w || !ku || !kv || !us || !vs || !pts) return fail(pl->ctx, NURBS_EINVAL, "NULL array");
     if ((pl->flags & NURBS_VALIDATE) && (!ws || ws_bytes < kWsHeader))
         return fail(pl->ctx, NURBS_EWORKSPACE, "NURBS_VALIDATE needs a workspace");
+    if (pl->schedule == NURBS_SCHED_DYNAMIC && (!ws || ws_bytes < kPlanHeader))
+        return fail(pl->ctx, NURBS_EWORKSPACE, "the dynamic schedule needs the first NURBS_PLAN_WS_HEADER bytes of "
+                                               "the plan's workspace");
     PlanArgs a = plan_args(pl, false, ws, ctrl, w, ku, kv, us, vs);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     hipEvent_t* ev = nullptr;
@@ -1145,8 +1183,11 @@ int nurbs_plan_fwd(nurbs_plan* pl, const float* ctrl, const float* w, const floa
         ++pl->calls_f;
         (void)hipEventRecord(ev[0], st);
     }
-    hipError_t e = pl->maxd == 5 ? launch_plan_fwd_d5(dim3(pl->grid_fwd), st, a, pts)
-                                 : launch_plan_fwd_d7(dim3(pl->grid_fwd), st, a, pts);
+    hipError_t e = a.queue ? launch_zero(st, reinterpret_cast<float*>(a.queue), (size_t)kQueues * kQueueStride)
+                           : hipSuccess;
+    if (e == hipSuccess)
+        e = pl->maxd == 5 ? launch_plan_fwd_d5(dim3(pl->grid_fwd), st, a, pts)
+                          : launch_plan_fwd_d7(dim3(pl->grid_fwd), st, a, pts);
     if (ev && e == hipSuccess) e = hipEventRecord(ev[1], st);
     if (e != hipSuccess) return hip_fail(pl->ctx, e, "launch plan forward");
     return NURBS_OK;
@@ -1174,6 +1215,8 @@ int nurbs_plan_bwd(nurbs_plan* pl, const float* ctrl, const float* w, const floa
         ++pl->calls_b;
         e = hipEventRecord(ev[0], st);
     }
+    if (pl->nb > 0 && e == hipSuccess && a.queue)
+        e = launch_zero(st, reinterpret_cast<float*>(a.queue), (size_t)kQueues * kQueueStride);
     if (pl->nb > 0 && e == hipSuccess)
         e = pl->maxd == 5 ? launch_plan_bwd_d5(dim3(pl->grid_bwd), st, a, grad_pts, slots, grad_mask)
                           : launch_plan_bwd_d7(dim3(pl->grid_bwd), st, a, grad_pts, slots, grad_mask);

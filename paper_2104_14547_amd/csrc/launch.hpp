@@ -20,6 +20,12 @@ struct UniformArgs {
     size_t tab_u_stride, tab_v_stride;
 };
 
+// Dynamic plan schedule: tiles are dealt to kQueues queues round-robin in
+// longest-first order; each queue's counter sits on its own 128-byte line
+// (kQueueStride ints apart) in the plan workspace's header.
+constexpr int kQueues = 16;
+constexpr int kQueueStride = 32;
+
 // Byte offset of the basis rows in a fixed-knot table of n samples (the
 // n int32 spans come first).
 __host__ __device__ inline size_t basis_table_split(int n) { return ((size_t)n * 4 + 255) & ~size_t(255); }
@@ -56,7 +62,8 @@ struct PlanArgs {
     const DevDesc* desc;
     const DevTile* tiles;     // natural order (finalize)
     const ExecTile* exec;     // execution records; wave w runs exec[wave_begin[w] .. wave_begin[w + 1])
-    const int* wave_begin;    // [nwaves + 1], assigned at plan creation
+    const int* wave_begin;    // [nwaves + 1], assigned at plan creation (static schedule)
+    int* queue;               // dynamic schedule: kQueues tile counters (zeroed before the launch); NULL: static
     int ntiles;
     int nwaves;               // persistent waves in the grid (grid * kWavesPerWG)
     unsigned flags;

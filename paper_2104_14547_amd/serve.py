@@ -295,7 +295,9 @@ class Server:
         n_uv, n_pts = int((nus + nvs).sum()), int(npts.sum())
         gsizes = [self._gcnt[sf] for sf in surfs]
         n_out = int(sum(sum(g) for g in gsizes))
-        ws_bytes = 256 + sum(r.ws_bytes - 256 for r in batch)
+        # one plan header for the batch, then every request's tile slots
+        H = N.NURBS_PLAN_WS_HEADER
+        ws_bytes = H + sum(r.ws_bytes - H for r in batch)
         region("uv", 4 * n_uv)
         region("target", 12 * n_pts)
         region("index", 8 * n_out)

@@ -77,8 +77,12 @@ def check_grads(batch, got, want, tol=GRAD_TOL, names=("ctrl", "w", "ku", "kv"))
     return worst
 
 
-def plan_run(batch, upstream, mask=nd.NURBS_GRAD_ALL, validate=False):
-    sb = nd.SurfaceBatch(batch.shapes, batch.offsets, device=0, validate=validate)
+def plan_run(batch, upstream, mask=nd.NURBS_GRAD_ALL, validate=False, schedule=None):
+    ctx = None
+    if schedule is not None:
+        ctx = nd.api.Context(0)
+        ctx.set_schedule(schedule)
+    sb = nd.SurfaceBatch(batch.shapes, batch.offsets, device=0, validate=validate, ctx=ctx)
     args = [T(getattr(batch, k)) for k in ("ctrl", "w", "ku", "kv", "us", "vs")]
     pts = sb.forward(*args)
     grads = sb.backward(*args, T(upstream), mask=mask)
@@ -244,6 +248,18 @@ def test_plan_is_deterministic_and_batch_invariant():
         sl = grad_slices(b, s)
         for name, x, y in zip(("ctrl", "w", "ku", "kv"), gg, g1):
             assert np.array_equal(x, y[sl[name]]), name
+
+
+def test_static_and_dynamic_schedules_agree_bitwise():
+    # the schedule only decides which wave runs a tile; each tile writes its
+    # own slot, so the two give the same bits, repeat after repeat
+    b = uneven_subset()
+    _, ps, gs = plan_run(b, b.upstream, schedule=nd.api.N.NURBS_SCHED_STATIC)
+    for _ in range(3):
+        _, pd, gd = plan_run(b, b.upstream, schedule=nd.api.N.NURBS_SCHED_DYNAMIC)
+        assert np.array_equal(ps, pd)
+        for x, y in zip(gs, gd):
+            assert np.array_equal(x, y)
 
 
 def test_plan_gradient_mask():
