@@ -537,7 +537,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="default tiles instead of the autotuned ones")
     ap.add_argument("--tiles", default="", metavar="FWD,BWD",
                     help="fixed sample points per forward,backward tile (skips the autotuner)")
-    ap.add_argument("--schedule", default="dynamic", choices=["dynamic", "static"],
+    ap.add_argument("--schedule", default="static", choices=["static", "dynamic"],
                     help="tile schedule with --tiles")
     ap.add_argument("--served-requests", type=int, default=20000,
                     help="requests per arrival rate in the served leg (0: skip it)")
@@ -632,7 +632,7 @@ def main():
     achieved = ab[dom] / (avg[dom] * 1e-3) / 1e9
     kernels = {names[k]: {"avg_ms": avg[k], "algorithmic_bytes": ab[k],
                           "achieved_GBs": ab[k] / (avg[k] * 1e-3) / 1e9} for k in avg}
-    chosen = tune["chosen"] if tune else {"schedule": "dynamic", "fwd_tile_points": 16384, "bwd_tile_points": 16384}
+    chosen = tune["chosen"] if tune else {"schedule": "static", "fwd_tile_points": 16384, "bwd_tile_points": 16384}
     traffic = traffic_for(names[dom], args.workload, chosen)
 
     result = {
