@@ -243,7 +243,10 @@ def uniform_leg(steps: int):
             "parity": par}
 
 
-VALU_PEAK_INSTR = 256 * 4 * 16 * 2.4e9  # lane-instructions/s: 256 CUs x 4 SIMD16 x 2.4 GHz (no packed FP32)
+# VALU issue peak in lane-instructions/s: 256 CUs x 4 SIMDs x 32 FP32 lanes per clock x 2.4 GHz, i.e. the
+# published 157.3 TFLOP/s FP32 vector rate counted as one instruction per FMA (a wave64 FP32 instruction
+# every 2 cycles per SIMD, without packed FP32)
+VALU_PEAK_INSTR = 256 * 4 * 32 * 2.4e9
 
 
 def _ev(torch):
@@ -472,7 +475,8 @@ def chamfer_leg(steps: int):
     return {"workload": f"chamfer_hausdorff_{n}x{m}_3d", "api": "nurbs_chamfer (CD, HD, both gradients); nurbs_nearest",
             "pairs_per_nearest": n * m, "steps": steps, "chamfer_ms": t_full, "nearest_ms": t_nn,
             "pair_evals_per_s": 2 * n * m / (t_full * 1e-3) if ok else None,
-            "roofline": {"bound": "alu", "kernel": "k_nn", "achieved": ach / 1e12, "peak": VALU_PEAK_INSTR / 1e12,
+            "roofline": {"bound": "alu", "kernel": "k_nn+k_nn_merge (nurbs_nearest)", "achieved": ach / 1e12,
+                         "peak": VALU_PEAK_INSTR / 1e12,
                          "unit": "T lane-instr/s", "frac": ach / VALU_PEAK_INSTR,
                          "instr_per_pair": instr},
             "parity": {"nearest_bit_exact": nn_exact, "cd_rel_err": abs(o[0] - cd) / cd,

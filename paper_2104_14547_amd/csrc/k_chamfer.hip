@@ -132,7 +132,25 @@ __global__ void __launch_bounds__(kWG) k_nn_merge(const int* __restrict__ pidx, 
     const long long o = (long long)b * stride + i;
     float best = pd2[o];
     int bi = pidx[o];
-    for (int r = 1; r < nranges; ++r) {
+    // eight ranges' partials loaded together, then compared in range order
+    constexpr int kU = 8;
+    int r = 1;
+    for (; r + kU <= nranges; r += kU) {
+        float d[kU];
+        int ix[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            d[u] = pd2[o + (long long)(r + u) * n];
+            ix[u] = pidx[o + (long long)(r + u) * n];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (d[u] < best) {
+                best = d[u];
+                bi = ix[u];
+            }
+    }
+    for (; r < nranges; ++r) {
         const float d = pd2[o + (long long)r * n];
         if (d < best) {
             best = d;
