@@ -681,6 +681,11 @@ UvArgs uv_args(const nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, in
     long long c = ((total + 2047) / 2048 + 255) / 256 * 256;
     c = std::max<long long>(c, a.lds_acc ? 1024 : 256);
     a.chunk = (int)std::min<long long>(c, 16384);
+    const size_t acc_lds = a.lds_acc ? 8 * (size_t)((a.nacc + 1) & ~1) : 0;
+    a.lds_net = acc_lds + 16 * (size_t)nu_c * nv_c <= kUvLdsDynMax ? 1 : 0;
+    // forward: 1024 pairs per workgroup when the net is staged (the staging
+    // is shared by more pairs), else 256
+    a.fchunk = a.lds_net ? 1024 : 256;
     a.err = (ctx->flags & NURBS_VALIDATE) ? reinterpret_cast<int*>(ws) : nullptr;
     return a;
 }

@@ -4,7 +4,8 @@
 //
 // Forward (k_uv_fwd): one lane per pair -- both spans by binary search in
 // LDS-staged knots, the p+1 and q+1 basis values, the (p+1)(q+1)-term
-// homogeneous sum read from the control net (L1/L2 resident), the rational
+// homogeneous sum from the control net (staged in LDS as (x, y, z, w) per
+// control point when it fits, else read through the caches), the rational
 // divide; optionally dS/du, dS/dv (Appendix A, eq. NURBSuDerivative1).
 //
 // Backward: per pair, with g = dL/dS, W = S'_w and R_ij = N_i N_j / W,
@@ -83,9 +84,27 @@ struct UvSurf {
     const float* __restrict__ w;
     const float* ku;  // LDS
     const float* kv;  // LDS
+    const float4* net;  // LDS copy of (x, y, z, w) per control point, or NULL (read ctrl, w)
     const float* __restrict__ uv;
     int p, q, nu_c, nv_c, npts;
 };
+
+// control point ij as (x, y, z, w)
+__device__ __forceinline__ float4 net_at(const UvSurf& s, int ij) {
+    if (s.net) return s.net[ij];
+    const float* c = s.ctrl + 3 * (size_t)ij;
+    return make_float4(c[0], c[1], c[2], s.w[ij]);
+}
+
+// Stage the surface's net in LDS (dst: ncp float4); every thread of the
+// workgroup takes part, and the caller synchronises.
+__device__ __forceinline__ void stage_net(const UvSurf& s, float4* dst) {
+    const int ncp = s.nu_c * s.nv_c;
+    for (int i = threadIdx.x; i < ncp; i += kWG) {
+        const float* c = s.ctrl + 3 * (size_t)i;
+        dst[i] = make_float4(c[0], c[1], c[2], s.w[i]);
+    }
+}
 
 __device__ __forceinline__ UvSurf uv_surf(const UvArgs& a, int b, float* lku, float* lkv) {
     UvSurf s;
@@ -99,6 +118,7 @@ __device__ __forceinline__ UvSurf uv_surf(const UvArgs& a, int b, float* lku, fl
     for (int i = threadIdx.x; i < nV; i += kWG) lkv[i] = gkv[i];
     s.ku = lku;
     s.kv = lkv;
+    s.net = nullptr;
     s.uv = a.uv + (a.uv_shared ? 0 : (size_t)b * a.npts * 2);
     s.p = a.p;
     s.q = a.q;
@@ -157,10 +177,8 @@ __device__ __forceinline__ void uv_point(const UvSurf& s, int k, UvPoint<PM, QM>
 #pragma unroll
         for (int h = 0; h <= QM; ++h) {
             if (h > s.q) break;
-            const int ij = row + h;
-            const float wt = s.w[ij];
-            const float* c = s.ctrl + 3 * (size_t)ij;
-            R = fma4(o.Nv[h], make_float4(c[0] * wt, c[1] * wt, c[2] * wt, wt), R);
+            const float4 c = net_at(s, row + h);
+            R = fma4(o.Nv[h], make_float4(c.x * c.w, c.y * c.w, c.z * c.w, c.w), R);
         }
         A = fma4(o.Nu[r], R, A);
     }
@@ -173,13 +191,18 @@ __device__ __forceinline__ void uv_point(const UvSurf& s, int k, UvPoint<PM, QM>
 template <int PM, int QM, bool DER>
 __global__ void __launch_bounds__(kWG) k_uv_fwd(UvArgs a, float* __restrict__ pts, float* __restrict__ du,
                                                float* __restrict__ dv) {
+    extern __shared__ float4 lnet[];
     __shared__ float lku[kWG], lkv[kWG];
     const int b = blockIdx.y;
-    const UvSurf s = uv_surf(a, b, lku, lkv);
+    UvSurf s = uv_surf(a, b, lku, lkv);
+    if (a.lds_net) {
+        stage_net(s, lnet);
+        s.net = lnet;
+    }
     __syncthreads();
-    if (a.err) uv_validate(a, s, blockIdx.x * kWG, min(s.npts, (int)(blockIdx.x + 1) * kWG));
-    const int k = blockIdx.x * kWG + threadIdx.x;
-    if (k >= s.npts) return;
+    const int k0 = blockIdx.x * a.fchunk, k1 = min(s.npts, k0 + a.fchunk);
+    if (a.err) uv_validate(a, s, k0, k1);
+    for (int k = k0 + (int)threadIdx.x; k < k1; k += kWG) {
     const size_t o = ((size_t)b * s.npts + k) * 3;
     if constexpr (!DER) {
         UvPoint<PM, QM> pt;
@@ -201,10 +224,8 @@ __global__ void __launch_bounds__(kWG) k_uv_fwd(UvArgs a, float* __restrict__ pt
 #pragma unroll
             for (int h = 0; h <= QM; ++h) {
                 if (h > s.q) break;
-                const int ij = row + h;
-                const float wt = s.w[ij];
-                const float* c = s.ctrl + 3 * (size_t)ij;
-                const float4 pw = make_float4(c[0] * wt, c[1] * wt, c[2] * wt, wt);
+                const float4 c = net_at(s, row + h);
+                const float4 pw = make_float4(c.x * c.w, c.y * c.w, c.z * c.w, c.w);
                 R = fma4(Nv[h], pw, R);
                 Rv = fma4(dNv[h], pw, Rv);
             }
@@ -217,6 +238,7 @@ __global__ void __launch_bounds__(kWG) k_uv_fwd(UvArgs a, float* __restrict__ pt
         if (pts) store3(pts + o, sx, sy, sz);
         if (du) store3(du + o, (Au.x - sx * Au.w) * inv, (Au.y - sy * Au.w) * inv, (Au.z - sz * Au.w) * inv);
         if (dv) store3(dv + o, (Av.x - sx * Av.w) * inv, (Av.y - sy * Av.w) * inv, (Av.z - sz * Av.w) * inv);
+    }
     }
 }
 
@@ -253,11 +275,11 @@ __device__ __forceinline__ void uv_terms(const UvSurf& s, int k, const float* __
         for (int h = 0; h <= QM; ++h) {
             if (h > s.q) break;
             const int ij = row + h;
-            const float wt = s.w[ij];
-            const float* c = s.ctrl + 3 * (size_t)ij;
-            float pg = (c[0] - S0) * g0;
-            pg = __builtin_fmaf(c[1] - S1, g1, pg);
-            pg = __builtin_fmaf(c[2] - S2, g2, pg);
+            const float4 c = net_at(s, ij);
+            const float wt = c.w;
+            float pg = (c.x - S0) * g0;
+            pg = __builtin_fmaf(c.y - S1, g1, pg);
+            pg = __builtin_fmaf(c.z - S2, g2, pg);
             if (want_pw) {
                 const float nn = pt.Nu[r] * pt.Nv[h] * inv;
                 const float nw = nn * wt;
@@ -300,9 +322,14 @@ struct EmitMax {
 template <int PM, int QM>
 __global__ void __launch_bounds__(kWG) k_uv_max(UvArgs a, const float* __restrict__ gpts, unsigned mask,
                                                unsigned* __restrict__ maxbits) {
+    extern __shared__ float4 lnet[];
     __shared__ float lku[kWG], lkv[kWG];
     const int b = blockIdx.y;
-    const UvSurf s = uv_surf(a, b, lku, lkv);
+    UvSurf s = uv_surf(a, b, lku, lkv);
+    if (a.lds_net) {
+        stage_net(s, lnet);
+        s.net = lnet;
+    }
     __syncthreads();
     const float* g = gpts + (size_t)b * s.npts * 3;
     EmitMax em{{0.f, 0.f, 0.f, 0.f}};
@@ -350,11 +377,16 @@ __global__ void __launch_bounds__(kWG) k_uv_acc(UvArgs a, const float* __restric
     extern __shared__ unsigned long long lacc[];
     __shared__ float lku[kWG], lkv[kWG];
     const int b = blockIdx.y;
-    const UvSurf s = uv_surf(a, b, lku, lkv);
+    UvSurf s = uv_surf(a, b, lku, lkv);
     const int nacc = a.nacc;
     unsigned long long* gacc = acc_all + (size_t)b * nacc;
     if (a.lds_acc)
         for (int i = threadIdx.x; i < nacc; i += kWG) lacc[i] = 0ull;
+    if (a.lds_net) {  // the net after the accumulators, at a 16-byte boundary
+        float4* lnet = reinterpret_cast<float4*>(lacc + (a.lds_acc ? ((nacc + 1) & ~1) : 0));
+        stage_net(s, lnet);
+        s.net = lnet;
+    }
     __syncthreads();
     double sc[4];
 #pragma unroll
@@ -408,9 +440,10 @@ __global__ void __launch_bounds__(kWG) k_uv_fin(UvArgs a, const unsigned* __rest
 
 template <int PM, int QM>
 hipError_t uv_fwd_launch(const UvArgs& a, hipStream_t st, float* pts, float* du, float* dv) {
-    const dim3 grid((unsigned)((a.npts + kWG - 1) / kWG), (unsigned)a.B);
-    if (du || dv) hipLaunchKernelGGL((k_uv_fwd<PM, QM, true>), grid, dim3(kWG), 0, st, a, pts, du, dv);
-    else hipLaunchKernelGGL((k_uv_fwd<PM, QM, false>), grid, dim3(kWG), 0, st, a, pts, du, dv);
+    const dim3 grid((unsigned)((a.npts + a.fchunk - 1) / a.fchunk), (unsigned)a.B);
+    const size_t lds = a.lds_net ? sizeof(float4) * (size_t)a.nu_c * a.nv_c : 0;
+    if (du || dv) hipLaunchKernelGGL((k_uv_fwd<PM, QM, true>), grid, dim3(kWG), lds, st, a, pts, du, dv);
+    else hipLaunchKernelGGL((k_uv_fwd<PM, QM, false>), grid, dim3(kWG), lds, st, a, pts, du, dv);
     return hipGetLastError();
 }
 
@@ -422,8 +455,9 @@ hipError_t uv_bwd_launch(const UvArgs& a, hipStream_t st, const float* gpts, uns
     if (e != hipSuccess) return e;
     if (a.npts > 0) {  // no pairs: the zeroed accumulators give zero gradients
         const dim3 grid((unsigned)((a.npts + a.chunk - 1) / a.chunk), (unsigned)a.B);
-        hipLaunchKernelGGL((k_uv_max<PM, QM>), grid, dim3(kWG), 0, st, a, gpts, mask, maxbits);
-        const size_t lds = a.lds_acc ? sizeof(unsigned long long) * (size_t)a.nacc : 0;
+        const size_t net = a.lds_net ? sizeof(float4) * (size_t)a.nu_c * a.nv_c : 0;
+        hipLaunchKernelGGL((k_uv_max<PM, QM>), grid, dim3(kWG), net, st, a, gpts, mask, maxbits);
+        const size_t lds = (a.lds_acc ? sizeof(unsigned long long) * (size_t)((a.nacc + 1) & ~1) : 0) + net;
         hipLaunchKernelGGL((k_uv_acc<PM, QM>), grid, dim3(kWG), lds, st, a, gpts, mask, maxbits, acc);
     }
     const long long items = (long long)a.B * a.nacc;

@@ -127,9 +127,12 @@ struct UvArgs {
     int chunk;    // pairs per backward workgroup
     int nacc;     // 64-bit accumulators per surface: 4 nu_c nv_c + nU + nV
     int lds_acc;  // accumulate in LDS first (nacc * 8 bytes fit)
+    int lds_net;  // stage the net in LDS (16 bytes per control point, beside the accumulators)
+    int fchunk;   // pairs per forward workgroup
     int* err;     // device error word (NURBS_VALIDATE) or NULL
 };
-constexpr int kUvLdsAccMax = 7424;  // accumulators a workgroup keeps in LDS (58 KiB)
+constexpr int kUvLdsAccMax = 7424;                 // accumulators a workgroup keeps in LDS (58 KiB)
+constexpr size_t kUvLdsDynMax = 60 * 1024 - 2048;  // dynamic LDS per workgroup (static: the knots)
 hipError_t launch_uv_fwd(const UvArgs& a, hipStream_t st, float* pts, float* du, float* dv);
 hipError_t launch_uv_bwd(const UvArgs& a, hipStream_t st, const float* gpts, unsigned mask, unsigned* maxbits,
                          unsigned long long* acc, float* gc, float* gw, float* gku, float* gkv);
