@@ -444,11 +444,13 @@ int nurbs_plan_bwd(nurbs_plan *plan, const float *ctrl, const float *w,
 int nurbs_plan_set_timing(nurbs_plan *plan, int max_calls);
 /* Waits for the recorded events and returns, per recorded call, the kernel
  * durations in milliseconds: fwd[i] the forward kernel; bwd[i] the backward
- * kernel and fin[i] the finalize kernel of backward call i.  Arrays hold at
- * least max_calls entries (any may be NULL); *n_fwd / *n_bwd receive the
- * number of entries written (the most recent calls, oldest first). */
-int nurbs_plan_read_timing(nurbs_plan *plan, float *fwd, int *n_fwd, float *bwd, float *fin,
-                           int *n_bwd);
+ * row-loop kernel, gat[i] its gather kernel (the v-contraction of the tile
+ * accumulators into dL/dPw rectangles; about 0 when neither dL/dP nor dL/dw
+ * was asked for) and fin[i] the finalize kernel of backward call i.  Arrays
+ * hold at least max_calls entries (any may be NULL); *n_fwd / *n_bwd receive
+ * the number of entries written (the most recent calls, oldest first). */
+int nurbs_plan_read_timing(nurbs_plan *plan, float *fwd, int *n_fwd, float *bwd, float *gat,
+                           float *fin, int *n_bwd);
 
 /* ------------------------------------------------------------------------
  * Test exports: the device span search and basis used by the kernels.

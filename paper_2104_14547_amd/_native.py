@@ -93,7 +93,7 @@ _SIGS = {
     "nurbs_plan_bwd": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u, _vp, _sz,
                             _vp]),
     "nurbs_plan_set_timing": (_i, [_vp, _i]),
-    "nurbs_plan_read_timing": (_i, [_vp, _fp, _ip, _fp, _fp, _ip]),
+    "nurbs_plan_read_timing": (_i, [_vp, _fp, _ip, _fp, _fp, _fp, _ip]),
     "nurbs_find_spans": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp]),
     "nurbs_basis": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp]),
     "nurbs_read_device_error": (_i, [_vp, _vp, _ip]),

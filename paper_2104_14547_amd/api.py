@@ -707,15 +707,16 @@ class SurfaceBatch:
         self._timing_slots = int(max_calls)
 
     def read_timing(self):
-        """Per recorded call: forward, backward and finalize kernel ms."""
+        """Per recorded call: forward, backward row-loop, gather and finalize kernel ms."""
         n = max(getattr(self, "_timing_slots", 0), 1)
         f = (ctypes.c_float * n)()
         b = (ctypes.c_float * n)()
+        g = (ctypes.c_float * n)()
         z = (ctypes.c_float * n)()
         nf, nb = ctypes.c_int(), ctypes.c_int()
-        _check(N.lib().nurbs_plan_read_timing(self.handle, f, ctypes.byref(nf), b, z, ctypes.byref(nb)),
+        _check(N.lib().nurbs_plan_read_timing(self.handle, f, ctypes.byref(nf), b, g, z, ctypes.byref(nb)),
                self.ctx.handle)
-        return (np.array(f[:nf.value]), np.array(b[:nb.value]), np.array(z[:nb.value]))
+        return (np.array(f[:nf.value]), np.array(b[:nb.value]), np.array(g[:nb.value]), np.array(z[:nb.value]))
 
     def read_device_error(self, stream=None) -> int:
         code = ctypes.c_int()
@@ -800,11 +801,11 @@ def autotune(shapes, offsets, inputs, upstream, device: int | None = None, candi
             plan.forward(ctrl, w, ku, kv, us, vs, out=pts)
             plan.backward(ctrl, w, ku, kv, us, vs, upstream, out=grads)
         torch.cuda.synchronize(dev)
-        f, b, z = plan.read_timing()
+        f, b, g, z = plan.read_timing()
         plan.set_timing(0)
         key = f"{names[sched]}:{cand}"
         report["fwd"][key] = float(np.median(f))
-        report["bwd"][key] = float(np.median(b + z))
+        report["bwd"][key] = float(np.median(b + g + z))
         plan.close()
         del plan
     # one schedule for both directions (a plan has one), then the best tiling of each

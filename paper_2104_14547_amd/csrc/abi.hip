@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -42,6 +43,7 @@ struct nurbs_plan {
     ExecTile* d_fexec = nullptr;  // forward execution records, wave order
     DevTile* d_btiles = nullptr;
     ExecTile* d_bexec = nullptr;  // backward execution records, wave order
+    ExecTile* d_gexec = nullptr;  // backward records by decreasing estimated gather work
     int* d_fbegin = nullptr;      // wave boundaries in d_fexec
     int* d_bbegin = nullptr;      // wave boundaries in d_bexec
     int2* d_fin = nullptr;        // finalize parts (surface, part), most expensive first
@@ -53,7 +55,7 @@ struct nurbs_plan {
     int maxd = 5;  // degree class of the persistent kernels (5 or 7)
     int schedule = NURBS_SCHED_STATIC;
     std::vector<char> staging;  // host copy of the tables (plans made in caller memory)
-    // tracing: event ring per direction (2 events per forward, 3 per backward)
+    // tracing: event ring per direction (2 events per forward, 4 per backward)
     int trace_slots = 0;
     std::vector<hipEvent_t> ev_f, ev_b;
     long long calls_f = 0, calls_b = 0;
@@ -61,7 +63,7 @@ struct nurbs_plan {
 
 // byte offsets of the device tables inside one allocation
 struct PlanLayout {
-    size_t desc, ftiles, fexec, btiles, bexec, fbegin, bbegin, fin, total;
+    size_t desc, ftiles, fexec, btiles, bexec, gexec, fbegin, bbegin, fin, total;
 };
 
 namespace {
@@ -317,6 +319,17 @@ int nurbs_surface_derivs(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c
     return NURBS_OK;
 }
 
+namespace {
+// The gather of a uniform-batch backward: only dL/dP and dL/dw read the
+// rectangles it writes.
+hipError_t launch_uniform_gather(const nurbs_ctx* ctx, hipStream_t st, const UniformArgs& a, int p, int q,
+                                 char* slots, size_t slot_sz, unsigned mask) {
+    if (!(mask & (NURBS_GRAD_CTRL | NURBS_GRAD_W))) return hipSuccess;
+    return q <= 5 ? launch_uniform_gat_d5(st, a, p, q, slots, slot_sz, ctx->num_cus)
+                  : launch_uniform_gat_d7(st, a, p, q, slots, slot_sz, ctx->num_cus);
+}
+}  // namespace
+
 int nurbs_surface_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, const float* ctrl,
                       const float* w, const float* ku, const float* kv, int nu_s, int nv_s, const float* us,
                       const float* vs, int uv_shared, const float* grad_pts, float* grad_ctrl, float* grad_w,
@@ -356,6 +369,7 @@ int nurbs_surface_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, c
 #define ND_CASE(P)                                                                                        \
     case P:                                                                                               \
         e = launch_uniform_bwd_p##P(q, grid, st, a, grad_pts, slots, g.slot, grad_mask);                  \
+        if (e == hipSuccess) e = launch_uniform_gather(ctx, st, a, p, q, slots, g.slot, grad_mask);      \
         if (e == hipSuccess)                                                                              \
             e = launch_uniform_fin_p##P(q, dim3((fin_items + kWavesPerWG - 1) / kWavesPerWG), st, a, slots,  \
                                         g.slot,                                                           \
@@ -469,6 +483,7 @@ int nurbs_surface_bwd_tab(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_
 #define ND_CASE(P)                                                                                        \
     case P:                                                                                               \
         e = launch_uniform_bwd_p##P(q, grid, st, a, grad_pts, slots, g.slot, grad_mask);                  \
+        if (e == hipSuccess) e = launch_uniform_gather(ctx, st, a, p, q, slots, g.slot, grad_mask);      \
         if (e == hipSuccess)                                                                              \
             e = launch_uniform_fin_p##P(q, dim3((fin_items + kWavesPerWG - 1) / kWavesPerWG), st, a, slots,  \
                                         g.slot, grad_ctrl, grad_w, nullptr, nullptr, grad_mask);          \
@@ -845,6 +860,14 @@ double tile_cost(const nurbs_desc& d, int rows, bool bwd) {
     return 12.0 + rows * (1.0 + 0.25 * (d.p + 1)) + crow * (0.5 + 0.35 * (d.q + 1));
 }
 
+// Estimated work of a backward tile's gather: its blocks of four control rows
+// by 16 control columns (the expected rows and columns the tile touches).
+double gather_cost(const nurbs_desc& d, int rows, int cols) {
+    const double crow = std::min<double>(d.nu_c, d.p + 1 + (double)rows * (d.nu_c - d.p) / std::max(d.nu_s, 1));
+    const double ccol = std::min<double>(d.nv_c, d.q + 1 + (double)cols * (d.nv_c - d.q) / std::max(d.nv_s, 1));
+    return std::ceil(crow / 4.0) * std::ceil(ccol / 16.0);
+}
+
 // Tiles by decreasing estimated cost (ties in tile order).
 std::vector<int> longest_first(const std::vector<double>& cost) {
     std::vector<int> idx(cost.size());
@@ -920,7 +943,7 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
     // tiles
     std::vector<DevDesc> dd(n);
     std::vector<DevTile> ft, bt;
-    std::vector<double> fcost, bcost;
+    std::vector<double> fcost, bcost, gcost;
     size_t slot_off = 0;
     const int cus = std::max(ctx->num_cus, 1);
     for (int s = 0; s < n; ++s) {
@@ -950,6 +973,7 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
                     slot_off += align16(slot_bytes(d.p, d.q, d.nu_c, d.nv_c, rb));
                     bt.push_back(t);
                     bcost.push_back(tile_cost(d, t.row1 - t.row0, true));
+                    gcost.push_back(gather_cost(d, t.row1 - t.row0, std::min(kWave, d.nv_s - t.col0)));
                     ++cnt;
                 }
         }
@@ -1013,12 +1037,13 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
     const size_t o_fx = o_ft + al(sizeof(DevTile) * std::max<size_t>(ft.size(), 1));
     const size_t o_bt = o_fx + al(sizeof(ExecTile) * std::max<size_t>(ft.size(), 1));
     const size_t o_bx = o_bt + al(sizeof(DevTile) * std::max<size_t>(bt.size(), 1));
-    const size_t o_fb = o_bx + al(sizeof(ExecTile) * std::max<size_t>(bt.size(), 1));
+    const size_t o_gx = o_bx + al(sizeof(ExecTile) * std::max<size_t>(bt.size(), 1));
+    const size_t o_fb = o_gx + al(sizeof(ExecTile) * std::max<size_t>(bt.size(), 1));
     const size_t o_bb = o_fb + al(sizeof(int) * (nwf + 1));
     const size_t o_fi = o_bb + al(sizeof(int) * (nwb + 1));
     const size_t total = o_fi + al(sizeof(int2) * std::max<size_t>(fin.size(), 1));
     if (!blob) {  // size query: no schedule, no tables
-        *lay = PlanLayout{o_desc, o_ft, o_fx, o_bt, o_bx, o_fb, o_bb, o_fi, total};
+        *lay = PlanLayout{o_desc, o_ft, o_fx, o_bt, o_bx, o_gx, o_fb, o_bb, o_fi, total};
         *out = pl;
         return NURBS_OK;
     }
@@ -1034,11 +1059,13 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
         r.us_off = x.us_off; r.vs_off = x.vs_off; r.pts_off = x.pts_off; r.slot_off = t.slot_off;
         return r;
     };
-    std::vector<ExecTile> fx, bx;
+    std::vector<ExecTile> fx, bx, gx;
     fx.reserve(fo.size());
     bx.reserve(bo.size());
+    gx.reserve(bt.size());
     for (int i : fo) fx.push_back(record(ft[i]));
     for (int i : bo) bx.push_back(record(bt[i]));
+    for (int i : longest_first(gcost)) gx.push_back(record(bt[i]));
     blob->assign(total, 0);
     char* hb = blob->data();
     if (n) memcpy(hb + o_desc, dd.data(), sizeof(DevDesc) * n);
@@ -1046,10 +1073,11 @@ int plan_build(nurbs_ctx* ctx, const nurbs_desc* host, int n, unsigned flags, nu
     if (!fx.empty()) memcpy(hb + o_fx, fx.data(), sizeof(ExecTile) * fx.size());
     if (!bt.empty()) memcpy(hb + o_bt, bt.data(), sizeof(DevTile) * bt.size());
     if (!bx.empty()) memcpy(hb + o_bx, bx.data(), sizeof(ExecTile) * bx.size());
+    if (!gx.empty()) memcpy(hb + o_gx, gx.data(), sizeof(ExecTile) * gx.size());
     memcpy(hb + o_fb, fbeg.data(), sizeof(int) * fbeg.size());
     memcpy(hb + o_bb, bbeg.data(), sizeof(int) * bbeg.size());
     if (!fin.empty()) memcpy(hb + o_fi, fin.data(), sizeof(int2) * fin.size());
-    *lay = PlanLayout{o_desc, o_ft, o_fx, o_bt, o_bx, o_fb, o_bb, o_fi, total};
+    *lay = PlanLayout{o_desc, o_ft, o_fx, o_bt, o_bx, o_gx, o_fb, o_bb, o_fi, total};
     *out = pl;
     return NURBS_OK;
 }
@@ -1061,6 +1089,7 @@ void plan_bind(nurbs_plan* pl, void* dev, const PlanLayout& lay) {
     pl->d_fexec = reinterpret_cast<ExecTile*>(base + lay.fexec);
     pl->d_btiles = reinterpret_cast<DevTile*>(base + lay.btiles);
     pl->d_bexec = reinterpret_cast<ExecTile*>(base + lay.bexec);
+    pl->d_gexec = reinterpret_cast<ExecTile*>(base + lay.gexec);
     pl->d_fbegin = reinterpret_cast<int*>(base + lay.fbegin);
     pl->d_bbegin = reinterpret_cast<int*>(base + lay.bbegin);
     pl->d_fin = reinterpret_cast<int2*>(base + lay.fin);
@@ -1153,6 +1182,7 @@ PlanArgs plan_args(nurbs_plan* pl, bool bwd, void* ws, const float* ctrl, const 
     a.desc = pl->d_desc;
     a.tiles = bwd ? pl->d_btiles : pl->d_ftiles;
     a.exec = bwd ? pl->d_bexec : pl->d_fexec;
+    a.gexec = bwd ? pl->d_gexec : nullptr;
     a.ntiles = bwd ? pl->nb : pl->nf;
     a.wave_begin = bwd ? pl->d_bbegin : pl->d_fbegin;
     a.nwaves = (bwd ? pl->grid_bwd : pl->grid_fwd) * kWavesPerWG;
@@ -1216,7 +1246,7 @@ int nurbs_plan_bwd(nurbs_plan* pl, const float* ctrl, const float* w, const floa
     hipError_t e = hipSuccess;
     hipEvent_t* ev = nullptr;
     if (pl->trace_slots > 0) {
-        ev = &pl->ev_b[3 * (size_t)(pl->calls_b % pl->trace_slots)];
+        ev = &pl->ev_b[4 * (size_t)(pl->calls_b % pl->trace_slots)];
         ++pl->calls_b;
         e = hipEventRecord(ev[0], st);
     }
@@ -1226,13 +1256,17 @@ int nurbs_plan_bwd(nurbs_plan* pl, const float* ctrl, const float* w, const floa
         e = pl->maxd == 5 ? launch_plan_bwd_d5(dim3(pl->grid_bwd), st, a, grad_pts, slots, grad_mask)
                           : launch_plan_bwd_d7(dim3(pl->grid_bwd), st, a, grad_pts, slots, grad_mask);
     if (ev && e == hipSuccess) e = hipEventRecord(ev[1], st);
+    if (pl->nb > 0 && e == hipSuccess && (grad_mask & (NURBS_GRAD_CTRL | NURBS_GRAD_W)))
+        e = pl->maxd == 5 ? launch_plan_gat_d5(st, a, slots, pl->ctx->num_cus)
+                          : launch_plan_gat_d7(st, a, slots, pl->ctx->num_cus);
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess)
         e = pl->maxd == 5
                 ? launch_plan_fin_d5(dim3((pl->nfin + kWavesPerWG - 1) / kWavesPerWG), st, a, slots, grad_ctrl,
                                      grad_w, grad_ku, grad_kv, grad_mask)
                 : launch_plan_fin_d7(dim3((pl->nfin + kWavesPerWG - 1) / kWavesPerWG), st, a, slots, grad_ctrl,
                                      grad_w, grad_ku, grad_kv, grad_mask);
-    if (ev && e == hipSuccess) e = hipEventRecord(ev[2], st);
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[3], st);
     if (e != hipSuccess) return hip_fail(pl->ctx, e, "launch plan backward");
     return NURBS_OK;
 }
@@ -1242,7 +1276,7 @@ int nurbs_plan_set_timing(nurbs_plan* pl, int max_calls) {
     trace_free(pl);
     if (max_calls == 0) return NURBS_OK;
     pl->ev_f.resize(2 * (size_t)max_calls);
-    pl->ev_b.resize(3 * (size_t)max_calls);
+    pl->ev_b.resize(4 * (size_t)max_calls);
     for (auto* v : {&pl->ev_f, &pl->ev_b})
         for (hipEvent_t& e : *v) {
             hipError_t r = hipEventCreate(&e);
@@ -1256,7 +1290,7 @@ int nurbs_plan_set_timing(nurbs_plan* pl, int max_calls) {
     return NURBS_OK;
 }
 
-int nurbs_plan_read_timing(nurbs_plan* pl, float* fwd, int* n_fwd, float* bwd, float* fin, int* n_bwd) {
+int nurbs_plan_read_timing(nurbs_plan* pl, float* fwd, int* n_fwd, float* bwd, float* gat, float* fin, int* n_bwd) {
     if (!pl) return fail(nullptr, NURBS_EINVAL, "plan is NULL");
     if (pl->trace_slots == 0) return fail(pl->ctx, NURBS_EINVAL, "timing is off");
     auto span = [&](std::vector<hipEvent_t>& ev, int per, long long calls, int j0, int j1, float* out,
@@ -1275,8 +1309,9 @@ int nurbs_plan_read_timing(nurbs_plan* pl, float* fwd, int* n_fwd, float* bwd, f
         return hipSuccess;
     };
     hipError_t r = span(pl->ev_f, 2, pl->calls_f, 0, 1, fwd, n_fwd);
-    if (r == hipSuccess) r = span(pl->ev_b, 3, pl->calls_b, 0, 1, bwd, n_bwd);
-    if (r == hipSuccess) r = span(pl->ev_b, 3, pl->calls_b, 1, 2, fin, nullptr);
+    if (r == hipSuccess) r = span(pl->ev_b, 4, pl->calls_b, 0, 1, bwd, n_bwd);
+    if (r == hipSuccess) r = span(pl->ev_b, 4, pl->calls_b, 1, 2, gat, nullptr);
+    if (r == hipSuccess) r = span(pl->ev_b, 4, pl->calls_b, 2, 3, fin, nullptr);
     return r ? hip_fail(pl->ctx, r, "read timing events") : NURBS_OK;
 }
 

@@ -19,10 +19,16 @@
 //   G_i(b) += Nu_r(a) h   for the window rows   -> dL/dPw after the v-sum
 //   E_r(a) = sum_b R_i(b) . h = dL/dNu_r(a)     (eq. NURBSvDerivative6)
 // When a control row leaves the window its accumulator G_i(b) is final for
-// the tile and is *flushed*: (i) f_h(b) += Pw[i][kb-q+h] . G_i(b) builds
-// dL/dNv_h(b); (ii) the q+1 products Nv_h(b) G_i(b) are summed over the
-// lanes that share a v-span by a segmented scan, and one lane per control
-// column writes the tile's partial dL/dPw row.  No atomics: each value is
+// the tile and is *flushed*: f_h(b) += Pw[i][kb-q+h] . G_i(b) builds
+// dL/dNv_h(b), and G_i(b) itself is stored, one float4 per lane, in the
+// tile's workspace slot, beside a table of the tile's column spans and basis.
+//
+// Gather, a kernel of its own: the stored G_i are contracted along v,
+// dL/dPw[i][j] = sum_b Nv_j(v_b) G_i(b), into the tile's partial dL/dPw
+// rectangle, a small banded matrix product (control columns x 64 samples,
+// times 64 samples x 4 values per control row) done on the matrix cores.
+// It is kept out of the row loop, whose registers are all in use.  No
+// atomics: each value is
 // written once to a tile-indexed workspace slot, and the finalize pass adds
 // slots in a fixed order, so results are bitwise reproducible and do not
 // depend on which wave ran which tile.
@@ -33,6 +39,7 @@
 // (Sec. 3.2.1), dL/dV_k likewise with f(b).
 #pragma once
 #include "device.hpp"
+#include "launch.hpp"
 
 namespace nd {
 
@@ -40,13 +47,20 @@ namespace nd {
 // workspace layout of one backward tile (bytes from the slot start):
 //   [0, 16)                      int4 header {i0, i1, j0, j1}
 //   [16, 32)                     float4 {cx, cy, cz, 0}: the tile's frame origin
-//   [32, 32 + 16*rect_cap)       float4 rect [(i1-i0+1)][(j1-j0+1)]
-//   then float e[rows][P+1], then float f[64][Q+1]
+//   [32, 32 + 16*nu_c*nv_c)      float4 rect [(i1-i0+1)][(j1-j0+1)]
+//   then float e[rows][P+1], then float f[64][Q+1] (each 16-byte aligned),
+//   then the column table: int first[64] (first control column, tile-relative,
+//   that sample column b touches; kGatherOff for inactive columns) and float
+//   nv[64][Q+1] (its basis values Nv_h(v_b)),
+//   then float4 gacc[nu_c][64]: the flushed accumulators G_i(b) of rows
+//   i0..i1 (zero for inactive columns), which the gather contracts along v
+//   into the rect.
 // The rect holds dL/dPw in the tile's translated frame (control points
 // P - c): the xyz part does not depend on the frame, the w part is
 // dL/dw - (P - c) . dL/dPw_xyz of the tile's points.
 // --------------------------------------------------------------------------
 constexpr int kSlotHead = 32;
+constexpr int kGatherOff = -(1 << 20);  // column-table entry of an inactive sample column
 
 struct SlotView {
     int* hdr;
@@ -54,18 +68,28 @@ struct SlotView {
     float4* rect;
     float* e;
     float* f;
+    float4* gacc;
+    int* ctab;
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
-__host__ __device__ inline size_t slot_bytes(int p, int q, int nu_c, int nv_c, int rows) {
+// byte offsets of the column table and of gacc in a slot
+__host__ __device__ inline size_t slot_ctab_off(int p, int q, int nu_c, int nv_c, int rows) {
     size_t b = kSlotHead + 16 * (size_t)nu_c * nv_c;
     b += align16(sizeof(float) * (size_t)rows * (p + 1));
     b += align16(sizeof(float) * (size_t)kWave * (q + 1));
     return b;
 }
+__host__ __device__ inline size_t slot_gacc_off(int p, int q, int nu_c, int nv_c, int rows) {
+    return slot_ctab_off(p, q, nu_c, nv_c, rows) + align16(sizeof(float) * (size_t)kWave * (q + 2));
+}
 
-__device__ __forceinline__ SlotView slot_view(char* base, int p, int nu_c, int nv_c, int rows) {
+__host__ __device__ inline size_t slot_bytes(int p, int q, int nu_c, int nv_c, int rows) {
+    return slot_gacc_off(p, q, nu_c, nv_c, rows) + 16 * (size_t)nu_c * kWave;
+}
+
+__device__ __forceinline__ SlotView slot_view(char* base, int p, int q, int nu_c, int nv_c, int rows) {
     SlotView v;
     v.hdr = reinterpret_cast<int*>(base);
     v.center = reinterpret_cast<float4*>(base + 16);
@@ -73,6 +97,8 @@ __device__ __forceinline__ SlotView slot_view(char* base, int p, int nu_c, int n
     char* e = base + kSlotHead + 16 * (size_t)nu_c * nv_c;
     v.e = reinterpret_cast<float*>(e);
     v.f = reinterpret_cast<float*>(e + align16(sizeof(float) * (size_t)rows * (p + 1)));
+    v.gacc = reinterpret_cast<float4*>(base + slot_gacc_off(p, q, nu_c, nv_c, rows));
+    v.ctab = reinterpret_cast<int*>(base + slot_ctab_off(p, q, nu_c, nv_c, rows));
     return v;
 }
 
@@ -522,32 +548,23 @@ __device__ __forceinline__ void der_tile(const Surf& sg, int q, int col0, int ro
 // --------------------------------------------------------------------------
 // backward tile
 // --------------------------------------------------------------------------
+// per-lane state of a backward tile's row loop
 template <int QM>
 struct BwdState {
     float Nv[QM + 1];
     int kb, jb;
     bool act;
-    int key_off;      // kb - kfirst for active lanes
-    int nkeys;        // distinct keys span kfirst..klast
     int j0, ncols;    // rect column range
-    int nsteps;       // in-row scan steps needed (ceil log2 of the longest run in a row)
-    bool cross;       // some segment crosses a 16-lane row boundary
-    float m[6];       // per-step "same segment as the source lane" multipliers
-    bool head;        // last lane of its segment
-    bool wide;        // the tile may touch more than 64 control columns (one gather pass per 64)
-    unsigned hl[2];   // bytes: head lane of key (lane - h) for h = 0..7, 0xFF = none
     int q;            // degree in v (uniform, <= QM)
     float f[QM + 1];  // dL/dNv_h(v_b) partial
     float cx, cy, cz; // the tile's frame origin (a control point of the tile, uniform)
 };
 
-// per-wave LDS of the backward tile, sized for degrees p <= PM
+// per-wave LDS of the backward tile's row loop, sized for degrees p <= PM
 template <int PM, int QM>
 struct BwdLdsT {
     float4 blk[kBlkCap];
     float knots[2][kWG];
-    float4 col[kWave];                      // run sums of one h, [head lane]
-    short head_of[kWG];                     // key offset -> head lane, or -1
     float ebuf[kEBatch * 4 * (PM + 1)];     // 16-lane partials of dL/dNu
 };
 
@@ -555,8 +572,6 @@ struct BwdLdsT {
 struct BwdLds {
     float4* blk;
     float* knots[2];
-    float4* col;
-    short* head_of;
     float* ebuf;
 };
 
@@ -566,11 +581,17 @@ __device__ __forceinline__ BwdLds bwd_lds(BwdLdsT<PM, QM>* t) {
     l.blk = t->blk;
     l.knots[0] = t->knots[0];
     l.knots[1] = t->knots[1];
-    l.col = t->col;
-    l.head_of = t->head_of;
     l.ebuf = t->ebuf;
     return l;
 }
+
+// Per-wave LDS of the gather: the current tile's column table, from which
+// the lanes build their operands of the contraction.
+template <int QM>
+struct GatTab {
+    int first[kWave];
+    float nv[kWave * (QM + 1)];
+};
 
 // One step of a segmented inclusive scan on the four components:
 // x += m * x[source lane], as one v_fmac_f32 per component that reads x
@@ -679,12 +700,12 @@ __device__ __forceinline__ float4 center4(float4 R, const St& st) {
                        __builtin_fmaf(-st.cz, R.w, R.z), R.w);
 }
 
-// Flush control row i (accumulator G) of the tile: dV partial and the rect
-// row i - i0 of dL/dPw.  Row i is staged in the block (or read from global).
+// Flush control row i (accumulator G) of the tile: the dV partial, and G
+// itself into the slot's gacc row i - i0 for the gather pass.  Row i is
+// staged in the block (or read from global).
 template <int QM, bool BLK>
 __device__ __forceinline__ void flush_row(const Surf& s, BwdState<QM>& st, const Block& bk, int i, int i0,
-                                          float4 G, float4* __restrict__ rect, BwdLds* L, bool want_pw,
-                                          bool want_kv) {
+                                          float4 G, float4* __restrict__ gacc, bool want_pw, bool want_kv) {
     const int lane = lane_opaque();
     const int q = st.q;
     if (want_kv) {
@@ -707,102 +728,164 @@ __device__ __forceinline__ void flush_row(const Surf& s, BwdState<QM>& st, const
                 }
         }
     }
-    if (!want_pw) return;
-    // control column j0 + c collects, for every h, the run sum of the key
-    // kfirst + c - h; one h at a time through a 64-entry LDS buffer
-    float4* out = rect + (size_t)(i - i0) * st.ncols;
-    if (!st.wide) {
-        // every column of the tile in one pass; head lanes from the per-tile table
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int h = 0; h <= QM; ++h) {
-            if (h > q) continue;
-            const float c = st.act ? st.Nv[h] : 0.f;
-            float4 x = make_float4(c * G.x, c * G.y, c * G.z, c * G.w);
-            seg_scan4(x, st);
-            if (st.head) L->col[lane] = x;
-            wave_lds_sync();
-            const int hl = (int)((st.hl[h >> 2] >> (8 * (h & 3))) & 0xFFu);
-            if (hl != 0xFF) {
-                const float4 v = L->col[hl];
-                acc.x += v.x;
-                acc.y += v.y;
-                acc.z += v.z;
-                acc.w += v.w;
-            }
-            wave_lds_sync();
-        }
-        if (lane < st.ncols) out[lane] = acc;
-        return;
-    }
-    // Wide tiles (rare: the tile's samples skip spans, so its control
-    // columns outnumber the lanes): one gather pass per 64 columns, each
-    // redoing the q+1 run sums, which keeps one accumulator live.  The
-    // column range has at most nv_c <= kWG - 2 entries, so four passes at most.
-    for (int c0 = 0; c0 < st.ncols; c0 += kWave) {
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int h = 0; h <= QM; ++h) {
-            if (h > q) continue;
-            const float c = st.act ? st.Nv[h] : 0.f;
-            float4 x = make_float4(c * G.x, c * G.y, c * G.z, c * G.w);
-            seg_scan4(x, st);
-            if (st.head) L->col[lane] = x;
-            wave_lds_sync();
-            const int o = lane + c0 - h;
-            const int hl = (o >= 0 && o < st.nkeys) ? (int)L->head_of[o] : -1;
-            if (hl >= 0) {
-                const float4 v = L->col[hl];
-                acc.x += v.x;
-                acc.y += v.y;
-                acc.z += v.z;
-                acc.w += v.w;
-            }
-            wave_lds_sync();
-        }
-        if (lane + c0 < st.ncols) out[lane + c0] = acc;
-    }
+    // inactive columns hold G = 0 (their dL/dS is zero), so the row is stored whole
+    if (want_pw) gacc[(size_t)(i - i0) * kWave + lane] = G;
 }
 
 // Column set-up of a backward tile (independent of the degree in u): the
-// lane's v-span and basis, and the segment structure of the spans.
+// lane's v-span and basis, and the tile's control-column range.
 template <int QM, bool TAB = false>
-__device__ __forceinline__ void bwd_columns(const Surf& s, int q, int col0, float vb, BwdState<QM>& st, BwdLds* L,
+__device__ __forceinline__ void bwd_columns(const Surf& s, int q, int col0, float vb, BwdState<QM>& st,
                                             const ColPre<QM>* pre = nullptr) {
-    const int lane = lane_id();
     st.q = q;
     int j0, ncols;
     st.kb = tile_columns<QM, TAB>(s, q, col0, vb, st.Nv, st.act, j0, ncols, pre);
     st.jb = st.kb - q;
 #pragma unroll
     for (int h = 0; h <= QM; ++h) st.f[h] = 0.f;
-    const int kfirst = j0 + q;
     st.j0 = j0;
     st.ncols = ncols;
-    st.nkeys = ncols - q;
-    st.key_off = st.kb - kfirst;
-    // runs of equal v-span; inactive lanes get keys of their own past the last span
-    const Runs rr = wave_runs(st.act ? st.kb : 0x40000000 + lane);
+}
+
+// One tile of the gather as its wave sees it: slot, offsets of the column
+// table and of gacc in it, degree in v.
+struct GatTile {
+    char* slot;
+    size_t ctab_off, gacc_off;
+    int q;
+};
+
+// A tile's header and this lane's column-table entry, loaded a tile ahead.
+template <int QM>
+struct GatPre {
+    int4 hd;
+    int first;
+    float nv[QM + 1];
+};
+
+template <int QM>
+__device__ __forceinline__ void gat_prefetch(const GatTile& t, GatPre<QM>& p) {
+    const int lane = lane_id();
+    p.hd = *reinterpret_cast<const int4*>(t.slot);
+    const int* ct = reinterpret_cast<const int*>(t.slot + t.ctab_off);
+    p.first = ct[lane];
+    const float* cn = reinterpret_cast<const float*>(ct + kWave) + lane * (t.q + 1);
 #pragma unroll
-    for (int s2 = 0; s2 < 6; ++s2) st.m[s2] = rr.m[s2];
-    st.nsteps = rr.nsteps;
-    st.cross = rr.cross;
-    st.head = st.act && rr.head;
-    for (int o = lane; o < st.nkeys; o += kWave) L->head_of[o] = (short)-1;
-    wave_lds_sync();
-    if (st.head) L->head_of[st.key_off] = (short)lane;
-    wave_lds_sync();
-    // control column j0 + lane + h collects key lane (offset lane) at degree index h:
-    // its head lane per h, for the first 64 columns
-    st.hl[0] = st.hl[1] = 0xFFFFFFFFu;
+    for (int h = 0; h <= QM; ++h) p.nv[h] = h <= t.q ? cn[h] : 0.f;
+}
+
+// The gather, by one workgroup: tiles k = blockIdx, blockIdx + gridDim, ...
+// of the source's order; within a tile, wave w takes the blocks w,
+// w + kWavesPerWG, ... (column block outer), so a tile with many blocks is
+// spread over the workgroup's waves.  For each tile, control rows i0..i1 and
+// control columns j0..j1 (slot header):
+//   rect[i - i0][jj] = sum_b M[jj][b] G_i(b),   M[jj][b] = Nv_{jj-first(b)}(v_b)
+// (zero outside 0..q; inactive columns b have G = 0), the v-contraction of
+// the flushed accumulators, with first(b) and Nv from the column table the
+// row loop wrote.  Per tile a small banded matrix product, (ncols x 64) by
+// (64 x 4 values per control row), computed with FP32 MFMA
+// (v_mfma_f32_16x16x4f32): blocks of 16 control columns by 16 values (four
+// control rows of G's four components), 64 samples in 16 steps of 4.
+// Operand layout of that instruction on a wave64 (lane l): A[l%16][l/16],
+// B[l/16][l%16], D[4(l/16)+v][l%16] for v = 0..3.  Latency is hidden in
+// software: each wave loads the next tile's record, header and table while
+// the current tile runs, and its next block's G values while the current
+// block is multiplied.  Each output value is one block's fixed sequence of
+// MFMAs: deterministic, and independent of which wave ran it.  Src supplies
+// fetch(k) (a raw tile record, loaded ahead) and unpack(raw, k).
+template <int QM, class Src>
+__device__ __forceinline__ void gather_tiles(int ntiles, const Src& src, GatTab<QM>* tab) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    const int lane = lane_id();
+    const int wv = uniform((int)(threadIdx.x / kWave));
+    const int lm = lane & 15, lk = lane >> 4;  // A row / B column; A column / B row (sample within a step)
+    const int rr = lm >> 2, cc = lm & 3;       // B column lm = (control row rr of the block, component cc)
+    const int G = (int)gridDim.x;
+    int k = (int)blockIdx.x;
+    if (k >= ntiles) return;
+    GatTile cur = src.unpack(src.fetch(k), k);
+    auto raw = src.fetch(k + G < ntiles ? k + G : k);
+    GatPre<QM> pc;
+    gat_prefetch<QM>(cur, pc);
+    for (;;) {
+        // this tile's table into the wave's LDS (the previous tile's reads of
+        // it came first: one wave, LDS in order)
+        tab->first[lane] = pc.first;
 #pragma unroll
-    for (int h = 0; h <= QM; ++h) {
-        const int o = lane - h;
-        const int v = (o >= 0 && o < st.nkeys) ? (int)L->head_of[o] : -1;
-        const unsigned byte = v >= 0 ? (unsigned)v : 0xFFu;
-        st.hl[h >> 2] = (st.hl[h >> 2] & ~(0xFFu << (8 * (h & 3)))) | (byte << (8 * (h & 3)));
+        for (int h = 0; h <= QM; ++h) tab->nv[lane * (QM + 1) + h] = pc.nv[h];
+        wave_lds_sync();
+        const int nrows = uniform(pc.hd.y - pc.hd.x + 1), ncols = uniform(pc.hd.w - pc.hd.z + 1);
+        const int q = cur.q;
+        const float* gacc = reinterpret_cast<const float*>(cur.slot + cur.gacc_off);
+        float* rect = reinterpret_cast<float*>(cur.slot + kSlotHead);
+        // the next tile: its record was loaded a tile ago; load the one after
+        // it, and the next tile's header and table
+        const int kn = k + G;
+        GatTile nxt = cur;
+        GatPre<QM> pn = pc;
+        if (kn < ntiles) {
+            nxt = src.unpack(raw, kn);
+            raw = src.fetch(kn + G < ntiles ? kn + G : kn);
+            gat_prefetch<QM>(nxt, pn);
+        }
+        // B operands of row block g: G_{4g + rr}(4 s4 + lk).cc (inactive
+        // columns hold zeros).  A row past the last is read as the last row:
+        // written data, reaching only output columns that are not stored, so
+        // no load is predicated and all 16 are in flight at once.
+        const int rlast = nrows - 1;
+        auto load_b = [&](int g, float B[16]) {
+            const float* src_row = gacc + ((size_t)min(4 * g + rr, rlast) * kWave + lk) * 4 + cc;
+#pragma unroll
+            for (int s4 = 0; s4 < 16; ++s4) B[s4] = src_row[s4 * 16];
+        };
+        const int ngr = (nrows + 3) >> 2, nmb = (ncols + 15) >> 4;
+        const int npairs = ngr * nmb;
+        if (wv < npairs) {
+            float Bc[16];
+            load_b(wv % ngr, Bc);
+            float A[16];
+            int amb = -1;
+            for (int pidx = wv; pidx < npairs; pidx += kWavesPerWG) {
+                const int mb = pidx / ngr, g = pidx - mb * ngr;
+                const int pn2 = pidx + kWavesPerWG;
+                float Bn[16];
+                if (pn2 < npairs) load_b(pn2 % ngr, Bn);
+                if (mb != amb) {
+                    // A: M[16 mb + lm][4 s4 + lk] for the 16 steps; all table
+                    // reads independent (clamped index, times a 0/1 mask; the
+                    // table holds finite values for every column)
+                    amb = mb;
+                    int off[16];
+#pragma unroll
+                    for (int s4 = 0; s4 < 16; ++s4) off[s4] = 16 * mb + lm - tab->first[4 * s4 + lk];
+#pragma unroll
+                    for (int s4 = 0; s4 < 16; ++s4) {
+                        const float x = tab->nv[(4 * s4 + lk) * (QM + 1) + min(max(off[s4], 0), QM)];
+                        A[s4] = x * ((off[s4] >= 0 && off[s4] <= q) ? 1.f : 0.f);
+                    }
+                }
+                f4v D = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s4 = 0; s4 < 16; ++s4)
+                    D = __builtin_amdgcn_mfma_f32_16x16x4f32(A[s4], Bc[s4], D, 0, 0, 0);
+                const int row = 4 * g + rr;
+                if (row < nrows) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int jj = 16 * mb + 4 * lk + v;
+                        if (jj < ncols) rect[((size_t)row * ncols + jj) * 4 + cc] = D[v];
+                    }
+                }
+#pragma unroll
+                for (int s4 = 0; s4 < 16; ++s4) Bc[s4] = Bn[s4];
+            }
+        }
+        if (kn >= ntiles) break;
+        k = kn;
+        cur = nxt;
+        pc = pn;
+        wave_lds_sync();
     }
-    st.wide = uniform((int)(st.nkeys + QM > kWave)) != 0;
 }
 
 // Finish a batch of nb rows of dL/dNu: add the four 16-lane partials of
@@ -839,6 +922,14 @@ __device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, B
     const bool want_kv = (mask & 8u) != 0;
     const int q = st.q;
     const int b = col0 + lane;
+    if (want_pw) {
+        // the gather's column table: this column's first control column and basis
+        out.ctab[lane] = st.act ? st.jb - st.j0 : kGatherOff;
+        float* nv = reinterpret_cast<float*>(out.ctab + kWave) + lane * (q + 1);
+#pragma unroll
+        for (int h = 0; h <= QM; ++h)
+            if (h <= q) nv[h] = st.Nv[h];
+    }
     float4 R[P + 1], G[P + 1];
     int cur = -1, i0 = 0;
     // dL/dS is loaded one row ahead of its use, straight into registers
@@ -876,7 +967,7 @@ __device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, B
                 // rows are non-decreasing, so the window only moves forward;
                 // each control row leaving it is flushed
                 while (cur < ka) {
-                    flush_row<QM, BLK>(s, st, bk, cur - P, i0, G[0], out.rect, L, want_pw, want_kv);
+                    flush_row<QM, BLK>(s, st, bk, cur - P, i0, G[0], out.gacc, want_pw, want_kv);
 #pragma unroll
                     for (int r = 0; r < P; ++r) {
                         R[r] = R[r + 1];
@@ -922,11 +1013,12 @@ __device__ __forceinline__ void bwd_rows_impl(const Surf& s, BwdState<QM>& st, B
     // flush the rows still in the window (all still staged)
     const int i1 = cur;
     for (int r = 0; r <= P; ++r) {
-        flush_row<QM, BLK>(s, st, bk, cur - P, i0, G[0], out.rect, L, want_pw, want_kv);
+        flush_row<QM, BLK>(s, st, bk, cur - P, i0, G[0], out.gacc, want_pw, want_kv);
 #pragma unroll
         for (int m = 0; m < P; ++m) G[m] = G[m + 1];
         ++cur;
     }
+
     if (want_kv) {
 #pragma unroll
         for (int h = 0; h <= QM; ++h)
@@ -975,7 +1067,7 @@ __device__ __forceinline__ void bwd_tile(const Surf& sg, int q, int col0, int ro
     }
     const Surf s = bwd_stage(sg, P, q, col0, row0, row1, L, in);
     BwdState<QM> st;
-    bwd_columns<QM, TAB>(s, q, col0, in.v, st, L, &cpre);
+    bwd_columns<QM, TAB>(s, q, col0, in.v, st, &cpre);
     bwd_rows<P, QM, TAB>(s, st, col0, row0, row1, in.u0, gpts, out, L, mask, &rpre);
 }
 
@@ -1303,6 +1395,35 @@ __device__ __forceinline__ void finalize_surface(const Surf& s, int ntiles, Tile
         finalize_part_pq<P, Q>(s, ntiles, tile_at, part, gctrl, gw, gku, gkv, mask, L);
         wave_lds_sync();
     }
+}
+
+// Surface s of a uniform batch (degrees p, q).
+__device__ __forceinline__ Surf uniform_surf(const UniformArgs& a, int s, int p, int q) {
+    Surf r;
+    const size_t cp = (size_t)a.nu_c * a.nv_c;
+    r.ctrl = a.ctrl + (size_t)s * cp * 3;
+    r.w = a.w + (size_t)s * cp;
+    r.ku = a.ku + (size_t)s * (a.nu_c + p + 1);
+    r.kv = a.kv + (size_t)s * (a.nv_c + q + 1);
+    r.us = a.us + (a.uv_shared ? 0 : (size_t)s * a.nu_s);
+    r.vs = a.vs + (a.uv_shared ? 0 : (size_t)s * a.nv_s);
+    r.nu_c = a.nu_c;
+    r.nv_c = a.nv_c;
+    r.nu_s = a.nu_s;
+    r.nv_s = a.nv_s;
+    r.tsu = nullptr;
+    r.tbu = nullptr;
+    r.tsv = nullptr;
+    r.tbv = nullptr;
+    if (a.tab_u) {  // fixed-knot tables: spans, then basis rows at the next 256-byte boundary
+        const char* tu = a.tab_u + (size_t)s * a.tab_u_stride;
+        const char* tv = a.tab_v + (size_t)s * a.tab_v_stride;
+        r.tsu = reinterpret_cast<const int*>(tu);
+        r.tbu = reinterpret_cast<const float*>(tu + basis_table_split(a.nu_s));
+        r.tsv = reinterpret_cast<const int*>(tv);
+        r.tbv = reinterpret_cast<const float*>(tv + basis_table_split(a.nv_s));
+    }
+    return r;
 }
 
 }  // namespace nd

@@ -62,6 +62,7 @@ struct PlanArgs {
     const DevDesc* desc;
     const DevTile* tiles;     // natural order (finalize)
     const ExecTile* exec;     // execution records; wave w runs exec[wave_begin[w] .. wave_begin[w + 1])
+    const ExecTile* gexec;    // backward: the same records by decreasing estimated gather work
     const int* wave_begin;    // [nwaves + 1], assigned at plan creation (static schedule)
     int* queue;               // dynamic schedule: kQueues tile counters (zeroed before the launch); NULL: static
     int ntiles;
@@ -102,7 +103,11 @@ ND_DECLARE_UNIFORM(7)
     hipError_t launch_plan_fin_d##M(dim3 grid, hipStream_t st, const PlanArgs& a, const char* slots,  \
                                     float* gc, float* gw, float* gku, float* gkv, unsigned mask);     \
     hipError_t occupancy_plan_fwd_d##M(int* blocks_per_cu);                                           \
-    hipError_t occupancy_plan_bwd_d##M(int* blocks_per_cu);
+    hipError_t occupancy_plan_bwd_d##M(int* blocks_per_cu);                                           \
+    /* gather (after the backward, before the finalize): plan tiles, uniform tiles; cus: compute units */ \
+    hipError_t launch_plan_gat_d##M(hipStream_t st, const PlanArgs& a, char* slots, int cus);         \
+    hipError_t launch_uniform_gat_d##M(hipStream_t st, const UniformArgs& a, int p, int q, char* slots, \
+                                       size_t slot_sz, int cus);
 ND_DECLARE_PLAN(5)
 ND_DECLARE_PLAN(7)
 #undef ND_DECLARE_PLAN
