@@ -246,10 +246,11 @@ def uniform_leg(steps: int):
             "parity": par}
 
 
-# VALU issue peak in lane-instructions/s: 256 CUs x 4 SIMDs x 32 FP32 lanes per clock x 2.4 GHz, i.e. the
-# published 157.3 TFLOP/s FP32 vector rate counted as one instruction per FMA (a wave64 FP32 instruction
-# every 2 cycles per SIMD, without packed FP32)
-VALU_PEAK_INSTR = 256 * 4 * 32 * 2.4e9
+# VALU issue peak in lane-instructions/s without packed FP32: 256 CUs x 4 SIMDs x 16 lanes per clock x
+# 2.4 GHz (a wave64 instruction every 4 cycles per SIMD).  The published 157.3 TFLOP/s FP32 vector rate is
+# this rate x 2 flops per FMA x 2 for packed FP32 (two values per lane per instruction), which the library
+# does not use; the 78.6 TFLOP/s FP64 vector rate is the same 39.3 T FMA/s x 2 flops.
+VALU_PEAK_INSTR = 256 * 4 * 16 * 2.4e9
 
 
 def _ev(torch):
