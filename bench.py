@@ -89,15 +89,25 @@ def traffic_for(kernel: str, workload: str, chosen: dict):
     return None
 
 
+def evict_mall(torch, flush):
+    """Fill ``flush`` (larger than the 256 MB MALL) and wait for the fill to
+    finish, including the write-back of its dirty lines at the end of the
+    kernel, so that the next timed region starts with the caches holding
+    none of the step's inputs and with no memory traffic of the fill still
+    in progress."""
+    flush.fill_(0.0)
+    torch.cuda.synchronize()
+
+
 def timed_steps(torch, step, n: int, flush=None):
     """Run ``step`` n times between HIP events on the current stream; with
-    ``flush`` (a large device buffer), fill it before each step, outside the
-    events.  Returns the per-step times in ms."""
+    ``flush`` (a large device buffer), evict the MALL before each step,
+    outside the events.  Returns the per-step times in ms."""
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
     torch.cuda.synchronize()
     for a, b in ev:
         if flush is not None:
-            flush.fill_(0.0)
+            evict_mall(torch, flush)
         a.record()
         step()
         b.record()
@@ -296,7 +306,7 @@ def curve_leg(steps: int):
     ev = [(_ev(torch), _ev(torch), _ev(torch)) for _ in range(steps)]
     torch.cuda.synchronize()
     for a, b, c in ev:
-        flush.fill_(0.0)
+        evict_mall(torch, flush)
         a.record()
         fwd()
         b.record()
@@ -385,7 +395,7 @@ def uv_leg(steps: int):
     ev = [(_ev(torch), _ev(torch), _ev(torch)) for _ in range(steps)]
     torch.cuda.synchronize()
     for a, b, c in ev:
-        flush.fill_(0.0)
+        evict_mall(torch, flush)
         a.record()
         fwd()
         b.record()
@@ -619,8 +629,9 @@ def main():
     # back to back, for reference: the MALL (256 MB) may still hold part of
     # the previous step's data
     t_bb = timed_steps(torch, step, args.steps, flush=None)
-    # the timed steps: before each, a 512 MB fill evicts the MALL, outside the
-    # events that time the step, so every step reads its inputs from HBM
+    # the timed steps: before each, a 512 MB fill evicts the MALL and is waited
+    # for, outside the events that time the step, so every step reads its
+    # inputs from HBM
     flush = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
     plan.set_timing(args.steps)
     step_ms = timed_steps(torch, step, args.steps, flush=flush)
@@ -666,8 +677,8 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "kernels": kernels,
         "step_algorithmic_GBs": (ab["fwd"] + ab["bwd"] + ab["fin"]) / (ms_step * 1e-3) / 1e9,
-        "timing": {"step_ms": "mean of per-step HIP events; a 512 MB fill evicts the MALL before each step, "
-                              "outside the events",
+        "timing": {"step_ms": "mean of per-step HIP events; a 512 MB fill evicts the MALL before each step "
+                              "and is waited for (host synchronisation), outside the events",
                    "back_to_back_ms_per_step": float(np.mean(t_bb)),
                    "back_to_back_pts_s": batch.n_points / (float(np.mean(t_bb)) * 1e-3)},
     }
