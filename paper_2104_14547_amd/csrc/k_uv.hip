@@ -89,11 +89,17 @@ struct UvSurf {
     int p, q, nu_c, nv_c, npts;
 };
 
-// control point ij as (x, y, z, w)
+// control point ij as (x, y, z, w): from the LDS copy (NET) or from ctrl, w.
+// Two compiled paths, so that the LDS reads stay LDS reads (one path with a
+// run-time choice let the compiler merge both into generic-address loads).
+template <bool NET>
 __device__ __forceinline__ float4 net_at(const UvSurf& s, int ij) {
-    if (s.net) return s.net[ij];
-    const float* c = s.ctrl + 3 * (size_t)ij;
-    return make_float4(c[0], c[1], c[2], s.w[ij]);
+    if constexpr (NET) {
+        return s.net[ij];
+    } else {
+        const float* c = s.ctrl + 3 * (size_t)ij;
+        return make_float4(c[0], c[1], c[2], s.w[ij]);
+    }
 }
 
 // Stage the surface's net in LDS (dst: ncp float4); every thread of the
@@ -161,7 +167,7 @@ struct UvPoint {
     float4 A;    // homogeneous sum (x w, y w, z w, w)
 };
 
-template <int PM, int QM>
+template <int PM, int QM, bool NET>
 __device__ __forceinline__ void uv_point(const UvSurf& s, int k, UvPoint<PM, QM>& o) {
     const float2 uv = *reinterpret_cast<const float2*>(s.uv + 2 * (size_t)k);
     o.u = clamp_param(s.ku, s.p, s.nu_c - 1, uv.x);
@@ -177,7 +183,7 @@ __device__ __forceinline__ void uv_point(const UvSurf& s, int k, UvPoint<PM, QM>
 #pragma unroll
         for (int h = 0; h <= QM; ++h) {
             if (h > s.q) break;
-            const float4 c = net_at(s, row + h);
+            const float4 c = net_at<NET>(s, row + h);
             R = fma4(o.Nv[h], make_float4(c.x * c.w, c.y * c.w, c.z * c.w, c.w), R);
         }
         A = fma4(o.Nu[r], R, A);
@@ -188,25 +194,14 @@ __device__ __forceinline__ void uv_point(const UvSurf& s, int k, UvPoint<PM, QM>
 // --------------------------------------------------------------------------
 // forward
 // --------------------------------------------------------------------------
-template <int PM, int QM, bool DER>
-__global__ void __launch_bounds__(kWG) k_uv_fwd(UvArgs a, float* __restrict__ pts, float* __restrict__ du,
-                                               float* __restrict__ dv) {
-    extern __shared__ float4 lnet[];
-    __shared__ float lku[kWG], lkv[kWG];
-    const int b = blockIdx.y;
-    UvSurf s = uv_surf(a, b, lku, lkv);
-    if (a.lds_net) {
-        stage_net(s, lnet);
-        s.net = lnet;
-    }
-    __syncthreads();
-    const int k0 = blockIdx.x * a.fchunk, k1 = min(s.npts, k0 + a.fchunk);
-    if (a.err) uv_validate(a, s, k0, k1);
+template <int PM, int QM, bool DER, bool NET>
+__device__ __forceinline__ void uv_fwd_range(const UvSurf& s, int b, int k0, int k1, float* __restrict__ pts,
+                                             float* __restrict__ du, float* __restrict__ dv) {
     for (int k = k0 + (int)threadIdx.x; k < k1; k += kWG) {
     const size_t o = ((size_t)b * s.npts + k) * 3;
     if constexpr (!DER) {
         UvPoint<PM, QM> pt;
-        uv_point<PM, QM>(s, k, pt);
+        uv_point<PM, QM, NET>(s, k, pt);
         const float inv = recip_fast(pt.A.w);
         store3(pts + o, pt.A.x * inv, pt.A.y * inv, pt.A.z * inv);
     } else {
@@ -224,7 +219,7 @@ __global__ void __launch_bounds__(kWG) k_uv_fwd(UvArgs a, float* __restrict__ pt
 #pragma unroll
             for (int h = 0; h <= QM; ++h) {
                 if (h > s.q) break;
-                const float4 c = net_at(s, row + h);
+                const float4 c = net_at<NET>(s, row + h);
                 const float4 pw = make_float4(c.x * c.w, c.y * c.w, c.z * c.w, c.w);
                 R = fma4(Nv[h], pw, R);
                 Rv = fma4(dNv[h], pw, Rv);
@@ -242,6 +237,24 @@ __global__ void __launch_bounds__(kWG) k_uv_fwd(UvArgs a, float* __restrict__ pt
     }
 }
 
+template <int PM, int QM, bool DER>
+__global__ void __launch_bounds__(kWG) k_uv_fwd(UvArgs a, float* __restrict__ pts, float* __restrict__ du,
+                                               float* __restrict__ dv) {
+    extern __shared__ float4 lnet[];
+    __shared__ float lku[kWG], lkv[kWG];
+    const int b = blockIdx.y;
+    UvSurf s = uv_surf(a, b, lku, lkv);
+    if (a.lds_net) {
+        stage_net(s, lnet);
+        s.net = lnet;
+    }
+    __syncthreads();
+    const int k0 = blockIdx.x * a.fchunk, k1 = min(s.npts, k0 + a.fchunk);
+    if (a.err) uv_validate(a, s, k0, k1);
+    if (a.lds_net) uv_fwd_range<PM, QM, DER, true>(s, b, k0, k1, pts, du, dv);
+    else uv_fwd_range<PM, QM, DER, false>(s, b, k0, k1, pts, du, dv);
+}
+
 // --------------------------------------------------------------------------
 // backward
 // --------------------------------------------------------------------------
@@ -250,11 +263,11 @@ __global__ void __launch_bounds__(kWG) k_uv_fwd(UvArgs a, float* __restrict__ pt
 // Gradient classes: 0 dP, 1 dw, 2 dU, 3 dV.
 
 // Every term of one pair, handed to emit(class, accumulator index, value).
-template <int PM, int QM, class Emit>
+template <int PM, int QM, bool NET, class Emit>
 __device__ __forceinline__ void uv_terms(const UvSurf& s, int k, const float* __restrict__ gpts, unsigned mask,
                                          Emit& emit) {
     UvPoint<PM, QM> pt;
-    uv_point<PM, QM>(s, k, pt);
+    uv_point<PM, QM, NET>(s, k, pt);
     const float inv = recip(pt.A.w);
     const float S0 = pt.A.x * inv, S1 = pt.A.y * inv, S2 = pt.A.z * inv;
     const float* gp = gpts + 3 * (size_t)k;
@@ -275,7 +288,7 @@ __device__ __forceinline__ void uv_terms(const UvSurf& s, int k, const float* __
         for (int h = 0; h <= QM; ++h) {
             if (h > s.q) break;
             const int ij = row + h;
-            const float4 c = net_at(s, ij);
+            const float4 c = net_at<NET>(s, ij);
             const float wt = c.w;
             float pg = (c.x - S0) * g0;
             pg = __builtin_fmaf(c.y - S1, g1, pg);
@@ -335,7 +348,10 @@ __global__ void __launch_bounds__(kWG) k_uv_max(UvArgs a, const float* __restric
     EmitMax em{{0.f, 0.f, 0.f, 0.f}};
     const int k0 = blockIdx.x * a.chunk, k1 = min(s.npts, k0 + a.chunk);
     if (a.err) uv_validate(a, s, k0, k1);
-    for (int k = k0 + (int)threadIdx.x; k < k1; k += kWG) uv_terms<PM, QM>(s, k, g, mask, em);
+    if (a.lds_net)
+        for (int k = k0 + (int)threadIdx.x; k < k1; k += kWG) uv_terms<PM, QM, true>(s, k, g, mask, em);
+    else
+        for (int k = k0 + (int)threadIdx.x; k < k1; k += kWG) uv_terms<PM, QM, false>(s, k, g, mask, em);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         float v = em.m[c];
@@ -395,10 +411,16 @@ __global__ void __launch_bounds__(kWG) k_uv_acc(UvArgs a, const float* __restric
     const int k0 = blockIdx.x * a.chunk, k1 = min(s.npts, k0 + a.chunk);
     if (a.lds_acc) {
         EmitAcc<true> em{{sc[0], sc[1], sc[2], sc[3]}, nullptr};
-        for (int k = k0 + (int)threadIdx.x; k < k1; k += kWG) uv_terms<PM, QM>(s, k, g, mask, em);
+        if (a.lds_net)
+            for (int k = k0 + (int)threadIdx.x; k < k1; k += kWG) uv_terms<PM, QM, true>(s, k, g, mask, em);
+        else
+            for (int k = k0 + (int)threadIdx.x; k < k1; k += kWG) uv_terms<PM, QM, false>(s, k, g, mask, em);
     } else {
         EmitAcc<false> em{{sc[0], sc[1], sc[2], sc[3]}, gacc};
-        for (int k = k0 + (int)threadIdx.x; k < k1; k += kWG) uv_terms<PM, QM>(s, k, g, mask, em);
+        if (a.lds_net)
+            for (int k = k0 + (int)threadIdx.x; k < k1; k += kWG) uv_terms<PM, QM, true>(s, k, g, mask, em);
+        else
+            for (int k = k0 + (int)threadIdx.x; k < k1; k += kWG) uv_terms<PM, QM, false>(s, k, g, mask, em);
     }
     if (a.lds_acc) {
         __syncthreads();

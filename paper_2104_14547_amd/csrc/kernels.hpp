@@ -38,6 +38,8 @@
 // reverse-mode knot derivative of each row's basis weighted with e(a)
 // (Sec. 3.2.1), dL/dV_k likewise with f(b).
 #pragma once
+#include <type_traits>
+
 #include "device.hpp"
 #include "launch.hpp"
 
@@ -1232,11 +1234,15 @@ __device__ __forceinline__ void fin_pw_chunk(const Surf& s, int ntiles, TileAt t
         ii[c] = ij / s.nv_c;
         jj[c] = ij - ii[c] * s.nv_c;
     }
-    // v: the tile's rect entries; c: its frame origin
-    auto load_tile = [&](int t, float4 v[kFinCp], float4& c) {
+    // v: the tile's rect entries; c: its frame origin.  The header comes from
+    // LDS or from the slot, in two compiled paths (one path with a run-time
+    // choice let the compiler merge both into generic-address loads).
+    auto load_tile = [&](auto hl, int t, float4 v[kFinCp], float4& c) {
         const char* slot = tile_at(t).slot;
         c = *reinterpret_cast<const float4*>(slot + 16);
-        const int4 h = hdr_lds ? L->hdr[t] : *reinterpret_cast<const int4*>(slot);
+        int4 h;
+        if constexpr (decltype(hl)::value) h = L->hdr[t];
+        else h = *reinterpret_cast<const int4*>(slot);
         const float4* rect = reinterpret_cast<const float4*>(slot + kSlotHead);
         const int pitch = h.w - h.z + 1;
 #pragma unroll
@@ -1258,19 +1264,23 @@ __device__ __forceinline__ void fin_pw_chunk(const Surf& s, int ntiles, TileAt t
         }
     };
     // two tiles' loads in flight at a time; sums still in tile order
-    int t = 0;
-    for (; t + 1 < ntiles; t += 2) {
-        float4 va[kFinCp], vb[kFinCp], ca, cb;
-        load_tile(t, va, ca);
-        load_tile(t + 1, vb, cb);
-        add(va, ca);
-        add(vb, cb);
-    }
-    if (t < ntiles) {
-        float4 va[kFinCp], ca;
-        load_tile(t, va, ca);
-        add(va, ca);
-    }
+    auto sum_tiles = [&](auto hl) {
+        int t = 0;
+        for (; t + 1 < ntiles; t += 2) {
+            float4 va[kFinCp], vb[kFinCp], ca, cb;
+            load_tile(hl, t, va, ca);
+            load_tile(hl, t + 1, vb, cb);
+            add(va, ca);
+            add(vb, cb);
+        }
+        if (t < ntiles) {
+            float4 va[kFinCp], ca;
+            load_tile(hl, t, va, ca);
+            add(va, ca);
+        }
+    };
+    if (hdr_lds) sum_tiles(std::true_type{});
+    else sum_tiles(std::false_type{});
 #pragma unroll
     for (int c = 0; c < kFinCp; ++c) {
         const int ij = base + c * kWave + lane;
