@@ -124,8 +124,10 @@ def test_spans_bit_exact_and_basis(case):
     want = np.array([O.find_span(U.astype(np.float64), p, float(v)) for v in x])
     assert np.array_equal(spans, want)
     Nb = H(nd.basis(T(U), p, T(x)))
-    # FP32 triangular recursion: about 3 ulp per degree level for values <= 1
-    atol = (3 * p + 1) * 2.0 ** -24
+    # FP32 triangular recursion: at most 7 roundings of relative error per
+    # degree level (left/right, their sum, the reciprocal, three products and
+    # sums), and the values are <= 1, so 7 p 2^-24 absolute
+    atol = 7 * p * 2.0 ** -24
     for i, v in enumerate(x):
         k, Nl, _, _ = O.basis_local(U.astype(np.float64), p, float(v))
         assert k == spans[i]
