@@ -469,6 +469,81 @@ int nurbs_basis(const float *knots, int n_knots, int p, const float *x, int nx,
  * (NURBS_OK if none) and clears it. */
 int nurbs_read_device_error(const void *ws, void *stream, int *code);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of evaluation + gradient requests on
+ * resident surfaces, in native threads.  A request names a resident surface
+ * and brings a parameter grid (us, vs) and target points T; it receives S on
+ * the grid (Sec. 3.1, eq. NURBS) and the gradients of
+ * L = sum_ab ||S(u_a, v_b) - T_ab||^2 with respect to the surface's control
+ * points, weights and knot vectors (Sec. 3.2: eq. NURBSuDerivative4,
+ * eq. NURBSvDerivative5, eq. NURBSvDerivative6), computed as one ragged plan
+ * per batch of requests.
+ *
+ * Batches: requests are taken in arrival order while the batch fits a slot's
+ * device memory and fewer than max_requests are taken; a request for a
+ * surface already in the forming batch stays queued for a later batch (its
+ * gradients would land at the same offsets); the first request that does not
+ * fit ends the batch.  Each of n_slots slots has its own stream, device
+ * arena of slot_bytes and pinned host buffer of slot_bytes, so up to n_slots
+ * batches are in flight.  A request's result does not depend on the other
+ * requests of its batch, bit for bit (the plan's tiles follow each surface's
+ * own shape; the tiling is the context default).
+ * ---------------------------------------------------------------------- */
+typedef struct nurbs_server nurbs_server;
+
+/*   device      : HIP device ordinal.
+ *   pool        : n_surf descriptors (host, copied): p, q, nu_c, nv_c and
+ *                 ctrl_off, w_off, ku_off, kv_off into the resident arrays;
+ *                 the sample fields are ignored.
+ *   ctrl, w, ku, kv : the resident surfaces (device), packed as `pool` says;
+ *                 the caller keeps them alive and unchanged until
+ *                 nurbs_server_destroy.
+ *   n_slots     : batches in flight, 1..16; max_requests 1..65536 per batch;
+ *                 slot_bytes >= 64 KiB.
+ * Allocates n_slots * (2 slot_bytes + the pool's gradient arrays) of device
+ * and pinned host memory and starts the engine and completion threads. */
+int nurbs_server_create(int device, const nurbs_desc *pool, int n_surf, const float *ctrl,
+                        const float *w, const float *ku, const float *kv, int n_slots,
+                        size_t slot_bytes, int max_requests, nurbs_server **out);
+/* Queues one request; thread-safe.
+ *   us [nu_s], vs [nv_s], target [nu_s][nv_s][3] : host memory, read when
+ *                 the request's batch is packed;
+ *   out         : host memory of 3 nu_s nv_s + 4 nu_c nv_c + (nu_c+p+1) +
+ *                 (nv_c+q+1) floats, written when the batch completes:
+ *                 S [nu_s][nv_s][3], dL/dP [nu_c][nv_c][3], dL/dw [nu_c][nv_c],
+ *                 dL/dU [nu_c+p+1], dL/dV [nv_c+q+1];
+ *   The caller owns all five buffers and keeps them until
+ *   nurbs_server_wait(id) has returned (or the server is destroyed).
+ *   t_arrival   : latency origin in seconds of CLOCK_MONOTONIC; < 0: now.
+ *   id          : receives the request id (ids count up from 0).
+ * NURBS_EINVAL for a bad surface index, NULL buffer or empty grid;
+ * NURBS_EWORKSPACE when the request alone does not fit a slot; no id is
+ * issued then. */
+int nurbs_server_submit(nurbs_server *srv, int surf, const float *us, int nu_s, const float *vs,
+                        int nv_s, const float *target, float *out, double t_arrival, int64_t *id);
+/* Blocks until request `id` has finished; returns NURBS_OK or the error of
+ * its batch (text in nurbs_server_last_error) and its latency in seconds
+ * (arrival to the moment its batch's results were copied out). */
+int nurbs_server_wait(nurbs_server *srv, int64_t id, double *latency);
+/* Batches launched, requests finished, and the lowest id not yet finished
+ * (every id below it has finished). */
+int nurbs_server_stats(nurbs_server *srv, int64_t *batches, int64_t *completed,
+                       int64_t *finished_below);
+/* Host time, in seconds, the engine thread spent forming, packing and
+ * launching batches and the completion thread spent copying results out
+ * (waits excluded): where a saturated server's host time goes. */
+int nurbs_server_busy(nurbs_server *srv, double *engine_s, double *completion_s);
+const char *nurbs_server_last_error(nurbs_server *srv);
+/* Serves every queued request, stops the threads and frees the slots. */
+int nurbs_server_destroy(nurbs_server *srv);
+/* The batch-formation rule alone (host logic, no device): n queued requests
+ * in arrival order with their surfaces and device bytes; a batch has
+ * fixed_bytes besides its requests' and holds at most max_requests.  Writes
+ * the indices taken, ascending, to take[0..*n_take).  At most
+ * 4 max_requests requests are passed over for a surface already taken. */
+int nurbs_server_admit(const int32_t *surf, const size_t *nbytes, int n, size_t capacity,
+                       size_t fixed_bytes, int max_requests, int32_t *take, int *n_take);
+
 #ifdef __cplusplus
 }
 #endif

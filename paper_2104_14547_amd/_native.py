@@ -50,6 +50,8 @@ EXPORTS = (
     "nurbs_surface_uv_ws_bytes", "nurbs_surface_uv_fwd", "nurbs_surface_uv_bwd",
     "nurbs_basis_table_bytes", "nurbs_basis_table_build", "nurbs_surface_fwd_tab", "nurbs_surface_bwd_tab",
     "nurbs_ctx_set_schedule",
+    "nurbs_server_create", "nurbs_server_submit", "nurbs_server_wait", "nurbs_server_stats",
+    "nurbs_server_last_error", "nurbs_server_destroy", "nurbs_server_admit", "nurbs_server_busy",
 )
 
 
@@ -66,6 +68,7 @@ _sz = ctypes.c_size_t
 _szp = ctypes.POINTER(ctypes.c_size_t)
 _ip = ctypes.POINTER(ctypes.c_int)
 _fp = ctypes.POINTER(ctypes.c_float)
+_i64p = ctypes.POINTER(ctypes.c_int64)
 
 _SIGS = {
     "nurbs_ctx_create": (_i, [_i, ctypes.POINTER(_vp)]),
@@ -117,6 +120,16 @@ _SIGS = {
     "nurbs_curve_fwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _sz, _vp]),
     "nurbs_curve_bwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _u, _vp, _sz,
                              _vp]),
+    "nurbs_server_create": (_i, [_i, ctypes.POINTER(nurbs_desc), _i, _vp, _vp, _vp, _vp, _i, _sz, _i,
+                                 ctypes.POINTER(_vp)]),
+    "nurbs_server_submit": (_i, [_vp, _i, _vp, _i, _vp, _i, _vp, _vp, ctypes.c_double, _i64p]),
+    "nurbs_server_wait": (_i, [_vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
+    "nurbs_server_stats": (_i, [_vp, _i64p, _i64p, _i64p]),
+    "nurbs_server_last_error": (ctypes.c_char_p, [_vp]),
+    "nurbs_server_busy": (_i, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "nurbs_server_destroy": (_i, [_vp]),
+    "nurbs_server_admit": (_i, [ctypes.POINTER(ctypes.c_int32), _szp, _i, _sz, _sz, _i,
+                                ctypes.POINTER(ctypes.c_int32), _ip]),
 }
 
 _lib = None
@@ -141,6 +154,27 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+_serve_py = None
+
+
+def serve_py():
+    """The CPython binding of the per-request serving calls, bound to the
+    loaded library (raises if it has not been built)."""
+    global _serve_py
+    if _serve_py is None:
+        L = lib()
+        try:
+            from . import _serve_py as m
+        except ImportError as e:
+            raise NativeLibraryMissing(
+                f"the serving binding _serve_py is missing ({e}): build it with "
+                "`python -c 'import __graft_entry__ as g; g.build()'`") from e
+        addr = lambda f: ctypes.cast(f, ctypes.c_void_p).value
+        m.bind(addr(L.nurbs_server_submit), addr(L.nurbs_server_wait))
+        _serve_py = m
+    return _serve_py
 
 
 def status_string(code: int) -> str:

@@ -2,7 +2,9 @@
 
 Each ``csrc/*.hip`` translation unit (one per degree in u for the uniform
 kernels, one per kind and degree class for the persistent kernels, the host
-ABI) is compiled in parallel and linked into one shared library.
+ABI) is compiled in parallel and linked into one shared library.  The
+per-request serving binding ``csrc/serve_py.c`` (CPython C API, host code
+only) is compiled with the host C compiler into ``_serve_py``.
 
 Packed-FP32 instructions are disabled (``-packed-fp32-ops``): the per-point
 arithmetic is plain scalar FP32 FMA.  No fast-math.  The per-point rational
@@ -17,6 +19,7 @@ import concurrent.futures as cf
 import os
 import subprocess
 import sys
+import sysconfig
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -24,6 +27,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnurbsdiff.so")
 OBJ = os.path.join(ROOT, "_build", "obj")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CC = os.environ.get("CC", "gcc")
+PYEXT = os.path.join(HERE, "_serve_py" + sysconfig.get_config_var("EXT_SUFFIX"))
 ARCH = "gfx950"
 
 CFLAGS = [
@@ -40,7 +45,7 @@ def units():
 
 def sources():
     return [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC))
-            if f.endswith((".hip", ".hpp", ".inc", ".h"))] + [os.path.join(ROOT, "include", "nurbsdiff.h")]
+            if f.endswith((".hip", ".hpp", ".inc", ".h", ".c"))] + [os.path.join(ROOT, "include", "nurbsdiff.h")]
 
 
 def _compile(src, extra, verbose):
@@ -72,13 +77,26 @@ def build(extra=None, out=LIB, verbose=False, jobs=None) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, out)
+    build_pyext(verbose)
     return out
 
 
+def build_pyext(verbose=False) -> str:
+    """Compile the CPython serving binding (host code only)."""
+    tmp = PYEXT + ".tmp"
+    cmd = [CC, "-O2", "-shared", "-fPIC", "-Wall", "-I", sysconfig.get_paths()["include"], "-o", tmp,
+           os.path.join(CSRC, "serve_py.c")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, PYEXT)
+    return PYEXT
+
+
 def is_stale() -> bool:
-    if not os.path.exists(LIB):
+    if not os.path.exists(LIB) or not os.path.exists(PYEXT):
         return True
-    t = os.path.getmtime(LIB)
+    t = min(os.path.getmtime(LIB), os.path.getmtime(PYEXT))
     return any(os.path.getmtime(s) > t for s in sources())
 
 

@@ -89,3 +89,31 @@ def test_plain_baseline_matches_server():
         np.testing.assert_allclose(x.pts, y.pts, rtol=0, atol=1e-5)
         for u, v in zip((x.grad_ctrl, x.grad_w, x.grad_ku, x.grad_kv), (y.grad_ctrl, y.grad_w, y.grad_ku, y.grad_kv)):
             np.testing.assert_allclose(u, v, rtol=0, atol=1e-4 * max(np.abs(v).max(), 1e-30))
+
+
+def test_concurrent_submitters_and_caller_buffers():
+    # four client threads submit at once, two of them into their own output
+    # buffers; every result is bitwise the one of the same request served alone
+    import threading
+    pool = pool_small()
+    reqs = make_requests(pool, 120, seed=14)
+    with Server(pool, slot_bytes=128 << 20, n_slots=1, max_requests=1) as one:
+        _, alone = run_load(one, reqs, rate=None)
+    got = [None] * len(reqs)
+    with Server(pool, slot_bytes=128 << 20, n_slots=3, max_requests=32) as srv:
+        def client(t):
+            mine = range(t, len(reqs), 4)
+            futs = []
+            for k in mine:
+                s, us, vs, T = reqs[k]
+                out = np.full(srv.out_floats(s, len(us), len(vs)), np.nan, np.float32) if t % 2 else None
+                futs.append((k, srv.submit(s, us, vs, T, out=out)))
+            for k, f in futs:
+                got[k] = f.result()
+        th = [threading.Thread(target=client, args=(t,)) for t in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+    for k in range(len(reqs)):
+        assert same(got[k], alone[k]), f"request {k}: differs from the request served alone"
