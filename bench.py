@@ -40,10 +40,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# host code of the serving engine: no part of the kernels or of their launches
+SERVING_SOURCES = ("serve_py.c", "server.hip")
+
+
 def kernel_source_digest() -> str:
+    """Digest of the sources the kernels and their launches are built from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2104_14547_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
+        if f in SERVING_SOURCES:
+            continue
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
