@@ -416,9 +416,15 @@ def run_load(server, requests, rate: float | None, seed: int = 5):
         arrivals = t0 + np.cumsum(gaps)
         futs = []
         for (s, us, vs, T), ta, o in zip(requests, arrivals, outs):
+            # wait for the scheduled arrival: sleep only through long gaps
+            # (the OS wakes a sleeper tens of microseconds late, and requests
+            # would then go out in bursts behind their schedule), spin on the
+            # clock for the rest
             now = time.perf_counter()
-            if ta > now:
-                time.sleep(ta - now)
+            if ta - now > 2e-3:
+                time.sleep(ta - now - 1e-3)
+            while time.perf_counter() < ta:
+                pass
             if o is None:
                 futs.append(server.submit(s, us, vs, T, t_arrival=float(ta)))
             else:
