@@ -45,10 +45,21 @@ double now_s() {
     return (double)t.tv_sec + 1e-9 * (double)t.tv_nsec;
 }
 
-// One contiguous run of floats: src offset, dst offset, length.
+// One contiguous run of floats: src offset, dst offset, length.  Runs are
+// cut into pieces of at most kSegChunk floats, one workgroup each, so that a
+// large request spreads over many workgroups.
 struct Seg {
     int64_t src, dst, n;
 };
+constexpr int64_t kSegChunk = 16384;
+
+int64_t seg_pieces(int64_t n) { return (n + kSegChunk - 1) / kSegChunk; }
+
+// Appends the pieces of the run (src, dst, n) at `out`; returns the new end.
+Seg* emit_run(Seg* out, int64_t src, int64_t dst, int64_t n) {
+    for (int64_t o = 0; o < n; o += kSegChunk) *out++ = Seg{src + o, dst + o, std::min(kSegChunk, n - o)};
+    return out;
+}
 
 // g[dst + i] = 2 (res[dst + i] - tgt[src + i]): the adjoint of the squared
 // distance, at the offsets where the forward wrote the request's points.
@@ -153,6 +164,7 @@ struct Slot {
     std::vector<Req> batch;
     std::vector<nurbs_desc> desc;
     std::vector<int64_t> res_off;  // float offset of each request's result block
+    std::vector<int64_t> tgt_off;  // float offset of each request's targets
     nurbs_plan* plan = nullptr;
     size_t res_o = 0;  // byte offset of the result region
     int rc = NURBS_OK;
@@ -236,6 +248,13 @@ int64_t out_floats(const nurbs_desc& d, int nu_s, int nv_s) {
     for (int k = 0; k < kGroups; ++k) n += grad_count(d, k);
     return n;
 }
+// segment records of a request: its residual pieces, its gradient pieces
+int64_t residual_segs(int nu_s, int nv_s) { return seg_pieces(3ll * nu_s * nv_s); }
+int64_t gather_segs(const nurbs_desc& d) {
+    int64_t n = 0;
+    for (int k = 0; k < kGroups; ++k) n += seg_pieces(grad_count(d, k));
+    return n;
+}
 
 void set_err(nurbs_server* s, const std::string& m) {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -256,19 +275,23 @@ int plan_err(nurbs_server* s, nurbs_ctx* c, int rc, const char* what) {
 int launch(nurbs_server* s, Slot& sl) {
     const int n = (int)sl.batch.size();
     sl.res_off.resize(n);
+    sl.tgt_off.resize(n);
     sl.desc.resize(n);
-    size_t n_uv = 0, n_tgt = 0, n_res = 0, ws = NURBS_PLAN_WS_HEADER, tb = 0;
+    size_t n_uv = 0, n_tgt = 0, n_res = 0, ws = NURBS_PLAN_WS_HEADER, tb = 0, nrs = 0, ngs = 0;
     for (int i = 0; i < n; ++i) {
         const Req& r = sl.batch[i];
         const size_t npts = (size_t)r.nu_s * r.nv_s;
         sl.res_off[i] = (int64_t)n_res;
+        sl.tgt_off[i] = (int64_t)n_tgt;
         n_res += (size_t)out_floats(s->pool[r.surf], r.nu_s, r.nv_s);
         n_uv += (size_t)r.nu_s + r.nv_s;
         n_tgt += 3 * npts;
         ws += r.ws - NURBS_PLAN_WS_HEADER;
         tb += r.tb;
+        nrs += (size_t)residual_segs(r.nu_s, r.nv_s);
+        ngs += (size_t)gather_segs(s->pool[r.surf]);
     }
-    const size_t nseg = (size_t)(1 + kGroups) * n;
+    const size_t nseg = nrs + ngs;
     const size_t o_tgt = al(4 * n_uv), o_seg = o_tgt + al(4 * n_tgt), o_res = o_seg + al(sizeof(Seg) * nseg);
     const size_t o_g = o_res + al(4 * n_res), o_ws = o_g + al(4 * n_res), o_tb = o_ws + al(ws);
     const size_t end = o_tb + al(tb);
@@ -280,7 +303,9 @@ int launch(nurbs_server* s, Slot& sl) {
     float* huv = reinterpret_cast<float*>(sl.host);
     float* htgt = reinterpret_cast<float*>(sl.host + o_tgt);
     Seg* hseg = reinterpret_cast<Seg*>(sl.host + o_seg);
-    size_t cu = 0, ct = 0;
+    Seg* rseg = hseg;        // residual pieces
+    Seg* gseg = hseg + nrs;  // gradient pieces
+    size_t cu = 0;
     for (int i = 0; i < n; ++i) {
         const Req& r = sl.batch[i];
         const nurbs_desc& pd = s->pool[r.surf];
@@ -294,12 +319,11 @@ int launch(nurbs_server* s, Slot& sl) {
         d.vs_off = (int64_t)cu;
         cu += r.nv_s;
         d.pts_off = sl.res_off[i];
-        hseg[i] = Seg{(int64_t)ct, sl.res_off[i], (int64_t)(3 * npts)};
-        ct += 3 * npts;
+        rseg = emit_run(rseg, sl.tgt_off[i], sl.res_off[i], (int64_t)(3 * npts));
         int64_t dst = sl.res_off[i] + (int64_t)(3 * npts);
         for (int k = 0; k < kGroups; ++k) {
             const int64_t c = grad_count(pd, k);
-            hseg[n + kGroups * i + k] = Seg{(int64_t)s->gbase[k] + grad_off(pd, k), dst, c};
+            gseg = emit_run(gseg, (int64_t)s->gbase[k] + grad_off(pd, k), dst, c);
             dst += c;
         }
     }
@@ -308,7 +332,7 @@ int launch(nurbs_server* s, Slot& sl) {
         const nurbs_desc& d = sl.desc[i];
         std::memcpy(huv + d.us_off, r.us, 4 * (size_t)r.nu_s);
         std::memcpy(huv + d.vs_off, r.vs, 4 * (size_t)r.nv_s);
-        std::memcpy(htgt + hseg[i].src, r.tgt, 4 * (size_t)hseg[i].n);
+        std::memcpy(htgt + sl.tgt_off[i], r.tgt, 12 * (size_t)r.nu_s * r.nv_s);
     });
     hipError_t e = hipMemcpyAsync(sl.arena, sl.host, o_seg + sizeof(Seg) * nseg, hipMemcpyHostToDevice, sl.st);
     if (e != hipSuccess) return hip_err(s, e, "hipMemcpyAsync(batch inputs)");
@@ -329,13 +353,13 @@ int launch(nurbs_server* s, Slot& sl) {
     const size_t wsn = o_tb - o_ws;
     rc = nurbs_plan_fwd(sl.plan, s->ctrl, s->w, s->ku, s->kv, uv, uv, res, wsp, wsn, sl.st);
     if (rc) return plan_err(s, s->ctx, rc, "forward");
-    hipLaunchKernelGGL(k_residual, dim3((unsigned)n), dim3(256), 0, sl.st, seg, res, tgt, g);
+    hipLaunchKernelGGL(k_residual, dim3((unsigned)nrs), dim3(256), 0, sl.st, seg, res, tgt, g);
     if ((e = hipGetLastError()) != hipSuccess) return hip_err(s, e, "launch residual");
     float* gf = sl.gflat;
     rc = nurbs_plan_bwd(sl.plan, s->ctrl, s->w, s->ku, s->kv, uv, uv, g, gf + s->gbase[0], gf + s->gbase[1],
                         gf + s->gbase[2], gf + s->gbase[3], NURBS_GRAD_ALL, wsp, wsn, sl.st);
     if (rc) return plan_err(s, s->ctx, rc, "backward");
-    hipLaunchKernelGGL(k_copy_segs, dim3((unsigned)(kGroups * n)), dim3(256), 0, sl.st, seg + n, gf, res);
+    hipLaunchKernelGGL(k_copy_segs, dim3((unsigned)ngs), dim3(256), 0, sl.st, seg + nrs, gf, res);
     if ((e = hipGetLastError()) != hipSuccess) return hip_err(s, e, "launch gradient gather");
     e = hipMemcpyAsync(sl.host + o_res, sl.arena + o_res, 4 * n_res, hipMemcpyDeviceToHost, sl.st);
     if (e != hipSuccess) return hip_err(s, e, "hipMemcpyAsync(results)");
@@ -558,7 +582,8 @@ int nurbs_server_submit(nurbs_server* s, int surf, const float* us, int nu_s, co
     const size_t npts = (size_t)nu_s * nv_s;
     const size_t nout = (size_t)out_floats(s->pool[surf], nu_s, nv_s);
     // parameters, targets, segment records, result and dL/dS blocks, workspace tiles, tables
-    r.nbytes = 4 * ((size_t)nu_s + nv_s) + 12 * npts + (1 + kGroups) * sizeof(Seg) + 2 * 4 * nout +
+    const size_t nseg = (size_t)(residual_segs(nu_s, nv_s) + gather_segs(s->pool[surf]));
+    r.nbytes = 4 * ((size_t)nu_s + nv_s) + 12 * npts + nseg * sizeof(Seg) + 2 * 4 * nout +
                (r.ws - NURBS_PLAN_WS_HEADER) + r.tb;
     if (s->fixed + r.nbytes > s->slot_bytes) return NURBS_EWORKSPACE;
     {

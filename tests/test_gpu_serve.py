@@ -117,3 +117,22 @@ def test_concurrent_submitters_and_caller_buffers():
             t.join()
     for k in range(len(reqs)):
         assert same(got[k], alone[k]), f"request {k}: differs from the request served alone"
+
+
+def test_large_request_spans_many_segment_pieces():
+    # 200 x 180 samples: the residual and the copies run in several pieces of
+    # at most 16384 floats; the result matches the per-request baseline
+    pool = pool_small()
+    us = np.linspace(0.0, 1.0, 200, dtype=np.float32)
+    vs = np.linspace(0.0, 1.0, 180, dtype=np.float32)
+    rng = np.random.Generator(np.random.PCG64(15))
+    T = rng.uniform(-0.2, 0.2, (200, 180, 3)).astype(np.float32)
+    reqs = [(5, us, vs, T), (6, us[:37], vs[:41], T[:37, :41].copy())]
+    with Server(pool, slot_bytes=64 << 20) as srv:
+        _, a = run_load(srv, reqs, rate=None)
+    with PlainServer(pool) as plain:
+        _, b = run_load(plain, reqs, rate=None)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(x.pts, y.pts, rtol=0, atol=1e-5)
+        for u, v in zip((x.grad_ctrl, x.grad_w, x.grad_ku, x.grad_kv), (y.grad_ctrl, y.grad_w, y.grad_ku, y.grad_kv)):
+            np.testing.assert_allclose(u, v, rtol=0, atol=1e-4 * max(np.abs(v).max(), 1e-30))
