@@ -194,7 +194,7 @@ def parity_all(batch, pts, grads, pts_tol=1e-5, grad_tol=1e-4):
 def served_leg(batch, n_req: int, seed: int = 4):
     """Continuous-batching server on the batch's surfaces (resident): closed-
     loop saturation, then Poisson arrivals at 0.5x, 0.8x and 1.0x of it (each
-    after an untimed tenth as long at the same rate), and the per-request
+    after an untimed run as long at the same rate), and the per-request
     plain-launch baseline at the same rates (fewer requests: it saturates far
     earlier)."""
     from paper_2104_14547_amd.serve import PlainServer, Server, make_requests, run_load
@@ -206,8 +206,9 @@ def served_leg(batch, n_req: int, seed: int = 4):
         out["saturation_req_s"] = sat["req_per_s"]
         out["saturation_pts_s"] = sat["pts_per_s"]
         for f in (0.5, 0.8, 1.0):
-            # a short untimed run at the same rate first: the measured run starts in steady state
-            run_load(srv, reqs[: max(1, n_req // 10)], rate=f * sat["req_per_s"], seed=seed + 2)
+            # an untimed run of the same length at the same rate first: the
+            # measured run starts in steady state
+            run_load(srv, reqs, rate=f * sat["req_per_s"], seed=seed + 2)
             st, _ = run_load(srv, reqs, rate=f * sat["req_per_s"], seed=seed + 1)
             st["load"] = f
             out["rates"].append(st)
