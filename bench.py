@@ -202,9 +202,15 @@ def served_leg(batch, n_req: int, seed: int = 4):
     out = {"requests_per_rate": n_req, "rates": []}
     with Server(batch, slot_bytes=1 << 30, n_slots=3, max_requests=512) as srv:
         run_load(srv, reqs[: min(200, n_req)], rate=None)  # warm-up
+        b0, (e0, c0) = srv.batches, srv.busy()
         sat, _ = run_load(srv, reqs, rate=None)
+        b1, (e1, c1) = srv.batches, srv.busy()
         out["saturation_req_s"] = sat["req_per_s"]
         out["saturation_pts_s"] = sat["pts_per_s"]
+        # host time of the native threads at saturation, per request
+        out["saturation_requests_per_batch"] = n_req / max(1, b1 - b0)
+        out["engine_us_per_request"] = (e1 - e0) / n_req * 1e6
+        out["completion_us_per_request"] = (c1 - c0) / n_req * 1e6
         for f in (0.5, 0.8, 1.0):
             # an untimed run of the same length at the same rate first: the
             # measured run starts in steady state
