@@ -665,11 +665,28 @@ def main():
     step_ms = timed_steps(torch, step, args.steps, flush=flush)
     kf, kb, kg, kz = plan.read_timing()
     plan.set_timing(0)
+    # for context, the same step captured once as a HIP graph and replayed
+    # (launch gaps gone), same eviction; the kernels' own durations cannot be
+    # read from events recorded inside a replay, so `value` and the roofline
+    # stay with the eager steps above
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    graph.replay()
+    torch.cuda.synchronize()
+    graph_ms = timed_steps(torch, graph.replay, args.steps, flush=flush)
+    del graph
     del flush
     ms_step = float(np.mean(step_ms))
     value = batch.n_points / (ms_step * 1e-3)
     log(f"[bench] {args.steps} steps: {ms_step:.4f} ms/step (MALL flushed), {value:.4e} pts/s; "
-        f"back to back {np.mean(t_bb):.4f} ms/step; "
+        f"back to back {np.mean(t_bb):.4f} ms/step; graph replay {np.mean(graph_ms):.4f} ms/step; "
         f"kernels fwd {kf.mean():.4f} ms, bwd {kb.mean():.4f} ms, gather {kg.mean():.4f} ms, "
         f"finalize {kz.mean():.4f} ms")
 
@@ -709,7 +726,9 @@ def main():
                               "512 MB read evict the caches (the read leaves them clean) and are waited for "
                               "(host synchronisation), outside the events",
                    "back_to_back_ms_per_step": float(np.mean(t_bb)),
-                   "back_to_back_pts_s": batch.n_points / (float(np.mean(t_bb)) * 1e-3)},
+                   "back_to_back_pts_s": batch.n_points / (float(np.mean(t_bb)) * 1e-3),
+                   "graph_replay_ms_per_step": float(np.mean(graph_ms)),
+                   "graph_replay_pts_s": batch.n_points / (float(np.mean(graph_ms)) * 1e-3)},
     }
     if tune and not tune.get("fixed"):
         result["autotune_ms"] = {d: {str(k): v for k, v in tune[d].items()} for d in ("fwd", "bwd")}
