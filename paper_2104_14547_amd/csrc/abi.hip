@@ -342,10 +342,10 @@ int nurbs_surface_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, c
     if (((grad_mask & NURBS_GRAD_CTRL) && !grad_ctrl) || ((grad_mask & NURBS_GRAD_W) && !grad_w) ||
         ((grad_mask & NURBS_GRAD_KU) && !grad_ku) || ((grad_mask & NURBS_GRAD_KV) && !grad_kv))
         return fail(ctx, NURBS_EINVAL, "NULL gradient output for a requested gradient");
-    if (!ctrl || !w || !ku || !kv || !us || !vs) return fail(ctx, NURBS_EINVAL, "NULL array");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (nu_s == 0 || nv_s == 0) {
-        // no samples: every gradient is zero
+        // no samples: every gradient is zero (no input is read, and empty
+        // sample arrays may come as NULL)
         const size_t cp = (size_t)B * nu_c * nv_c;
         hipError_t e = hipSuccess;
         if (grad_mask & NURBS_GRAD_CTRL) e = launch_zero(st, grad_ctrl, cp * 3);
@@ -354,6 +354,7 @@ int nurbs_surface_bwd(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_c, c
         if (!e && (grad_mask & NURBS_GRAD_KV)) e = launch_zero(st, grad_kv, (size_t)B * (nv_c + q + 1));
         return e ? hip_fail(ctx, e, "zero fill") : NURBS_OK;
     }
+    if (!ctrl || !w || !ku || !kv || !us || !vs) return fail(ctx, NURBS_EINVAL, "NULL array");
     if (!grad_pts) return fail(ctx, NURBS_EINVAL, "NULL grad_pts");
     const UniformGeom g = uniform_geom(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
     const size_t need = kWsHeader + (size_t)g.tiles_b * g.slot;
@@ -458,15 +459,15 @@ int nurbs_surface_bwd_tab(nurbs_ctx* ctx, int B, int p, int q, int nu_c, int nv_
     if (grad_mask == 0 || B == 0) return NURBS_OK;
     if (((grad_mask & NURBS_GRAD_CTRL) && !grad_ctrl) || ((grad_mask & NURBS_GRAD_W) && !grad_w))
         return fail(ctx, NURBS_EINVAL, "NULL gradient output for a requested gradient");
-    if (!ctrl || !w || !ku || !kv || !us || !vs) return fail(ctx, NURBS_EINVAL, "NULL array");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (nu_s == 0 || nv_s == 0) {
+    if (nu_s == 0 || nv_s == 0) {  // no samples: zero gradients, no input read
         const size_t cp = (size_t)B * nu_c * nv_c;
         hipError_t e = hipSuccess;
         if (grad_mask & NURBS_GRAD_CTRL) e = launch_zero(st, grad_ctrl, cp * 3);
         if (!e && (grad_mask & NURBS_GRAD_W)) e = launch_zero(st, grad_w, cp);
         return e ? hip_fail(ctx, e, "zero fill") : NURBS_OK;
     }
+    if (!ctrl || !w || !ku || !kv || !us || !vs) return fail(ctx, NURBS_EINVAL, "NULL array");
     if (!grad_pts || !tab_u || !tab_v) return fail(ctx, NURBS_EINVAL, "NULL grad_pts or table");
     const UniformGeom g = uniform_geom(ctx, B, p, q, nu_c, nv_c, nu_s, nv_s);
     const size_t need = kWsHeader + (size_t)g.tiles_b * g.slot;

@@ -203,6 +203,37 @@ def test_edge_cases_uniform_and_plan(i):
         assert np.array_equal(x, y), "plan and uniform backward differ"
 
 
+def test_empty_sample_grids_write_zero_gradients():
+    # surfaces with no rows or no columns of samples: no points, and every
+    # gradient of theirs is written as exactly zero (outputs are overwritten,
+    # never accumulated), through the plan beside non-empty surfaces and
+    # through the uniform calls alone
+    parts = [one_surface(70, 3, 3, 8, 8, 20, 30), one_surface(71, 2, 4, 9, 7, 0, 17),
+             one_surface(72, 4, 2, 6, 10, 13, 0), one_surface(73, 2, 3, 5, 6, 9, 11)]
+    b = W.pack("empty_grids", parts)
+    S_or, G_or = oracle_both(b, b.upstream)
+    sb = nd.SurfaceBatch(b.shapes, b.offsets, device=0)
+    args = [T(getattr(b, k)) for k in ("ctrl", "w", "ku", "kv", "us", "vs")]
+    pts = sb.forward(*args)
+    outs = tuple(torch.full_like(x, float("nan")) for x in args[:4])
+    grads = sb.backward(*args, T(b.upstream), out=outs)
+    torch.cuda.synchronize()
+    pts, grads = H(pts), [H(g) for g in grads]
+    check_points(b, pts, S_or)
+    check_grads(b, grads, G_or)
+    for s in (1, 2):
+        sl = grad_slices(b, s)
+        for name, g in zip(("ctrl", "w", "ku", "kv"), grads):
+            assert np.array_equal(g[sl[name]], np.zeros_like(g[sl[name]])), f"surface {s} grad {name} not zero"
+    for nu_s, nv_s in ((0, 12), (12, 0)):
+        u = [one_surface(80 + j, 3, 2, 7, 6, nu_s, nv_s) for j in range(2)]
+        u[1]["us"], u[1]["vs"] = u[0]["us"], u[0]["vs"]
+        ub = W.pack("empty_uniform", u)
+        _, g = uniform_run(ub, ub.upstream)
+        for x in g:
+            assert np.array_equal(x, np.zeros_like(x)), f"uniform {nu_s}x{nv_s}: gradient not zero"
+
+
 # --------------------------------------------------------------------------
 # ragged batches (plan)
 # --------------------------------------------------------------------------
