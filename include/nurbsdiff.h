@@ -34,8 +34,9 @@
  *  - Sample vectors us, vs must be non-decreasing (a tensor-product grid
  *    in the order it is stored).
  *  - An empty grid (nu_s or nv_s = 0, or B = 0) is valid: a forward writes
- *    nothing, a backward writes zero gradients; neither reads an input
- *    array, so those may be NULL.
+ *    nothing, a backward writes zero gradients.  The uniform-batch calls
+ *    (nurbs_surface_*) then read no input array, so those may be NULL; in a
+ *    ragged plan an empty surface is one entry among others.
  *  - Layouts (row-major): ctrl [nu_c][nv_c][3], w [nu_c][nv_c],
  *    ku [nu_c+p+1], kv [nv_c+q+1], us [nu_s], vs [nv_s],
  *    pts / grad_pts [nu_s][nv_s][3].
