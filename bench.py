@@ -199,7 +199,9 @@ def served_leg(batch, n_req: int, seed: int = 4):
     earlier)."""
     from paper_2104_14547_amd.serve import PlainServer, Server, make_requests, run_load
     reqs = make_requests(batch, n_req, seed=seed)
-    out = {"requests_per_rate": n_req, "rates": []}
+    out = {"requests_per_rate": n_req, "rates": [],
+           "note": "native engine; the client's output arrays are allocated and touched before each run's clock "
+                   "starts; latency from each request's scheduled arrival to its result"}
     with Server(batch, slot_bytes=1 << 30, n_slots=3, max_requests=512) as srv:
         run_load(srv, reqs[: min(200, n_req)], rate=None)  # warm-up
         b0, (e0, c0) = srv.batches, srv.busy()
